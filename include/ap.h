@@ -1,0 +1,194 @@
+/*
+ * ap.h -- C ABI of the alternating-projection (AP) solver for Gaussian-process
+ * kernel systems on AMD MI355X (gfx950).
+ *
+ * Problem (Section 2, "Hyperparameter Training" and "Linear Solves"; Algorithm 1
+ * input/output): solve the batched system K^ W = B for W = K^^{-1} B, where
+ *   K^ = K + sigma^2 I,  K_ij = s * k(x_i, x_j),
+ * k is an RBF or Matern kernel with one lengthscale per feature (Section 5,
+ * "Datasets and Models"), B holds l right-hand sides.
+ *
+ * The method (Section 3, Algorithm 1): partition [n] into m = ceil(n/b) blocks
+ * of b consecutive rows (the last block holds the remainder), cache a factor of
+ * every diagonal block K^_{I,I} once per hyperparameter setting ("Cached
+ * Cholesky Factors"), then repeat epochs of m block updates
+ *   W_I <- W_I + K^_{I,I}^{-1} R_I                (eq. text_update_of_w)
+ *   R   <- R   - K^_{:,I} K^_{I,I}^{-1} R_I       (eq. text_update_of_r)
+ * with the block I chosen cyclically or by the modified Gauss-Southwell rule
+ * I = argmax_I ||R_{I,:}||_F^2 (eq. approximate_gauss_southwell), until the mean
+ * over columns of ||r_c|| / ||b_c|| is below a tolerance (Section 5,
+ * "Alternating Projection Details").
+ *
+ * Conventions for every entry point:
+ *  - Matrices are row-major. [dev] marks device (HBM) pointers, [host] host
+ *    pointers. Every [dev] buffer belongs to the caller; the library never
+ *    allocates or frees device memory. The handle borrows X and the workspace
+ *    for its whole life.
+ *  - Every call returns an ap_status. Nothing is thrown across the ABI, and
+ *    nothing aborts or exits. Out-parameters are left untouched on error unless
+ *    stated otherwise.
+ *  - Work is enqueued on the given HIP stream in stream order. Only
+ *    ap_factor_blocks, ap_solve, ap_rel_residual and ap_residual with a non-NULL
+ *    col_rel synchronize that stream. A handle is used by one host thread at a
+ *    time, and calls that overlap on one handle race.
+ *  - Errors the device detects (a non-positive pivot, a non-finite residual)
+ *    are kept in a status word in the workspace and reported by the next
+ *    synchronizing call.
+ */
+#ifndef AP_H
+#define AP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AP_OK = 0,
+  AP_NOT_CONVERGED = 1,      /* warning: max_epochs reached above tolerance */
+  AP_ERR_INVALID_ARG = -1,   /* a pointer, size or option is out of range */
+  AP_ERR_NOT_PD = -2,        /* a block K^_{I,I} has a non-positive Cholesky pivot */
+  AP_ERR_NONFINITE = -3,     /* NaN or Inf reached the residual norms */
+  AP_ERR_WORKSPACE = -4,     /* the workspace is smaller than ap_workspace_bytes */
+  AP_ERR_HIP = -5,           /* a HIP runtime call failed */
+  AP_ERR_UNSUPPORTED = -6    /* a size this build does not handle (see limits) */
+} ap_status;
+
+typedef enum { AP_RBF = 0, AP_MATERN32 = 1, AP_MATERN52 = 2 } ap_kernel;
+
+/* Block selection (Section 3, "Block Selection"): AP_CYCLIC takes block
+ * (u mod m) at update u of every epoch, starting at block 0; AP_GREEDY takes
+ * argmax_I ||R_{I,:}||_F^2, ties to the lowest block index; an epoch is m
+ * selections either way. */
+typedef enum { AP_CYCLIC = 0, AP_GREEDY = 1 } ap_order;
+
+/* Arithmetic of the fused residual update (the kernel tiles K^_{:,I} and their
+ * product with the block step). Block factors, block solves, W and the true
+ * residual are FP64 in both; R is FP32 in both.
+ *  AP_TILE_FP32: r^2 by exact differencing in FP32, kernel map in FP32, product
+ *                with the step on FP32 matrix cores.
+ *  AP_TILE_BF16: x.x' on BF16 matrix cores with a two-term (hi + lo) split of
+ *                every feature, kernel map in FP32, tile and step rounded to
+ *                BF16 for the product, FP32 accumulation. */
+typedef enum { AP_TILE_FP32 = 0, AP_TILE_BF16 = 1 } ap_tile;
+
+/* Limits of this build: 1 <= d <= 20, 1 <= l <= 32, 1 <= b <= 4096, b <= n,
+ * n < 2^31. Larger sizes return AP_ERR_UNSUPPORTED. */
+typedef struct {
+  int64_t n;                  /* number of points, >= 1 */
+  int32_t d;                  /* features per point */
+  int32_t l;                  /* right-hand sides (columns of B, W, R) */
+  int32_t b;                  /* block size; m = ceil(n / b) blocks */
+  int32_t kernel;             /* ap_kernel */
+  const double* lengthscale;  /* [host] d lengthscales, each > 0 (copied) */
+  double outputscale;         /* s > 0 */
+  double noise;               /* sigma^2 >= 0, added on the diagonal by index */
+  int32_t order;              /* ap_order */
+  int32_t tile;               /* ap_tile */
+  int32_t refine_every;       /* ap_solve: replace R by the FP64 true residual
+                                 after every k-th epoch; 0 = never */
+  double tol;                 /* ap_solve: stop when the ratio is < tol */
+  int32_t min_epochs;         /* ap_solve: never stop before this many epochs */
+  int32_t max_epochs;         /* ap_solve: stop after this many epochs */
+} ap_config;
+
+/* Per-problem device state, all [dev], n x l row-major:
+ *  B: right-hand sides (FP32, read only), W: weights (FP64), R: residual (FP32). */
+typedef struct {
+  const float* B;
+  double* W;
+  float* R;
+} ap_state;
+
+typedef struct {
+  int32_t epochs;             /* epochs run */
+  int32_t refines;            /* FP64 true-residual passes run */
+  double rho_maintained;      /* mean_c ||R_c|| / ||B_c|| of the maintained R */
+  double rho_true;            /* the same for B - K^ W in FP64 (NaN if not computed) */
+  double t_epochs;            /* seconds in epochs (HIP events) */
+  double t_refine;            /* seconds in true-residual passes */
+} ap_stats;
+
+typedef struct ap_problem* ap_handle;
+
+/* Bytes of device workspace a problem of this shape needs (factors m b^2 FP64
+ * plus O(n (d + l)) of staging). Returns 0 if cfg is NULL or invalid. */
+size_t ap_workspace_bytes(const ap_config* cfg);
+
+/* Validate cfg, lay out the workspace, prepare the features and cache the
+ * inverse of every diagonal block K^_{I,I} (Section 3, "Cached Cholesky
+ * Factors": a batched FP64 Cholesky of all blocks, then the inverse from the
+ * factor, so each block solve is one FP64 product).
+ *  X   [dev]  n x d FP32, borrowed until ap_destroy.
+ *  ws  [dev]  at least ap_workspace_bytes(cfg) bytes, borrowed; 256-byte aligned.
+ *  out [host] receives the handle on AP_OK.
+ *  bad_block [host, may be NULL] receives the first failing block on
+ *             AP_ERR_NOT_PD.
+ * Synchronizes the stream once. */
+ap_status ap_factor_blocks(const ap_config* cfg, const float* X, void* ws, size_t ws_bytes,
+                           hipStream_t stream, ap_handle* out, int64_t* bad_block);
+
+/* Algorithm 1 initialization: W = 0, R = B; also caches ||B_c|| and, for the
+ * greedy order, the first selection. Asynchronous. */
+ap_status ap_reset(ap_handle h, const ap_state* st, hipStream_t stream);
+
+/* Run `epochs` epochs of m block updates on each of `count` problems (h[i],
+ * st[i]); each problem's arithmetic is the same whatever count is. After each
+ * epoch the maintained-residual ratio is stored on the device (read it with
+ * ap_rel_residual). Asynchronous. */
+ap_status ap_epoch(const ap_handle* h, const ap_state* st, int32_t count, int32_t epochs,
+                   hipStream_t stream);
+
+/* One block update on block `block` (0 <= block < m): the inner loop body of
+ * Algorithm 1. Asynchronous. */
+ap_status ap_update(ap_handle h, const ap_state* st, int32_t block, hipStream_t stream);
+
+/* Synchronize the stream and read the maintained residual ratio after the last
+ * epoch: *rho = mean_c ||R_c|| / ||B_c|| (a zero column of B counts 0);
+ * col_ratio [host, may be NULL] receives the l per-column ratios. Returns
+ * AP_ERR_NONFINITE if a norm was NaN or Inf. */
+ap_status ap_rel_residual(ap_handle h, hipStream_t stream, double* rho, double* col_ratio);
+
+/* Algorithm 1 with the stopping rule: reset, then epochs until rho < tol with
+ * at least min_epochs epochs, or max_epochs. Every refine_every epochs, and on
+ * a tolerance hit when refine_every > 0 or tile == AP_TILE_BF16, R is replaced
+ * by the FP64 true residual (which is exact by Lemma residual_equality) and the
+ * test is repeated on it. Synchronizes once per epoch. Returns AP_OK,
+ * AP_NOT_CONVERGED or an error; out [host, may be NULL] gets the statistics. */
+ap_status ap_solve(ap_handle h, const ap_state* st, hipStream_t stream, ap_stats* out);
+
+/* True residual B - K^ W over all n^2 kernel entries in FP64 (Lemma
+ * residual_equality), written as FP32 to R_out [dev] (NULL: st->R, which
+ * refines the maintained residual). col_rel [host, may be NULL] receives the l
+ * ratios ||r_c|| / ||b_c|| of the FP64 values; passing it synchronizes. */
+ap_status ap_residual(ap_handle h, const ap_state* st, float* R_out, double* col_rel,
+                      hipStream_t stream);
+
+/* Copy the cached inverse of block j, len_j x len_j FP64 row-major, to dst
+ * [dev] (len_j = b, or the remainder for the last block). Asynchronous. */
+ap_status ap_block_inverse(ap_handle h, int32_t j, double* dst, hipStream_t stream);
+
+/* Per-phase timing: when enabled, HIP events are recorded on the stream around
+ * every launch group of this handle, in five phases: 0 block solve, 1 fused
+ * residual update, 2 greedy selection, 3 epoch-end check, 4 FP64 true
+ * residual. Enabling (or disabling) clears the totals. */
+ap_status ap_profile(ap_handle h, int32_t enable);
+
+/* Synchronize the stream and read the totals since the last ap_profile call:
+ * seconds [host, 5] and launches [host, 5], in the phase order above. */
+ap_status ap_profile_read(ap_handle h, hipStream_t stream, double* seconds, int64_t* launches);
+
+/* Free the host-side handle. The caller frees X and the workspace afterwards. */
+void ap_destroy(ap_handle h);
+
+/* Static description of a status code. */
+const char* ap_status_str(ap_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -41,6 +41,19 @@
 
 #include "ap_oracle.h"
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads the OpenMP loops use (1 without OpenMP). */
+int32_t apo_num_threads(void) {
+#ifdef _OPENMP
+  return (int32_t)omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
 /* ---- kernel function (Section 2 "Notation"; Section 5 kernels) ---------- */
 
 /* Squared ARD distance r^2 = sum_k ((x_k - y_k) / ell_k)^2, exact differencing. */
@@ -124,6 +137,14 @@ int64_t apo_cholesky(double* A, int64_t len) {
   return -1;
 }
 
+/* Factor the single diagonal block j into Lj (len_j x len_j). Returns -1 on
+ * success, else the non-positive pivot's index. */
+int64_t apo_factor_one(const apo_config* c, const double* X, int64_t j, double* Lj) {
+  int64_t s = apo_block_start(c, j), len = apo_block_len(c, j);
+  apo_khat_block(c, X, s, s + len, s, s + len, Lj);
+  return apo_cholesky(Lj, len);
+}
+
 /* Factor every diagonal block K^_{I,I}, I in P. Block j's factor occupies
  * L[j*b*b ...] as a len_j x len_j row-major matrix. Returns -1 on success, else
  * the first failing block, with its pivot index in *bad_pivot. */
@@ -180,21 +201,28 @@ void apo_apply_update(const apo_config* c, const double* X, double* R, int64_t b
   }
 }
 
-/* One AP update on block blk (inner loop of Algorithm 1):
+/* One AP update on block blk (inner loop of Algorithm 1), given that block's
+ * factor Lj:
  *   W_I += K^_{I,I}^{-1} R_I          (eq. text_update_of_w)
  *   R   -= K^_{:,I} K^_{I,I}^{-1} R_I  (eq. text_update_of_r)
  * If delta_out is not NULL, the step K^_{I,I}^{-1} R_I (len x l) is copied there. */
-void apo_update(const apo_config* c, const double* X, const double* L, double* W, double* R,
-                int64_t blk, double* delta_out) {
+void apo_update_block(const apo_config* c, const double* X, const double* Lj, double* W,
+                      double* R, int64_t blk, double* delta_out) {
   int64_t s = apo_block_start(c, blk), len = apo_block_len(c, blk);
   int32_t l = c->l;
   double* delta = (double*)malloc(sizeof(double) * (size_t)(len * l));
-  apo_block_solve(L + blk * (int64_t)c->b * c->b, len, l, R + s * l, delta);
+  apo_block_solve(Lj, len, l, R + s * l, delta);
   for (int64_t q = 0; q < len; ++q)
     for (int32_t col = 0; col < l; ++col) W[(s + q) * l + col] += delta[q * l + col];
   apo_apply_update(c, X, R, blk, delta);
   if (delta_out) memcpy(delta_out, delta, sizeof(double) * (size_t)(len * l));
   free(delta);
+}
+
+/* The same with block blk's factor taken from the array of all factors. */
+void apo_update(const apo_config* c, const double* X, const double* L, double* W, double* R,
+                int64_t blk, double* delta_out) {
+  apo_update_block(c, X, L + blk * (int64_t)c->b * c->b, W, R, blk, delta_out);
 }
 
 /* ---- block selection (Section 3 "Block Selection") ---------------------- */

@@ -29,6 +29,7 @@ typedef struct {
   int32_t min_epochs, max_epochs;
 } apo_config;
 
+int32_t apo_num_threads(void);
 double apo_kernel(const apo_config* c, const double* x, const double* y);
 void apo_khat_block(const apo_config* c, const double* X, int64_t i0, int64_t i1, int64_t j0,
                     int64_t j1, double* out);
@@ -36,10 +37,13 @@ int64_t apo_num_blocks(const apo_config* c);
 int64_t apo_block_start(const apo_config* c, int64_t j);
 int64_t apo_block_len(const apo_config* c, int64_t j);
 int64_t apo_cholesky(double* A, int64_t len);
+int64_t apo_factor_one(const apo_config* c, const double* X, int64_t j, double* Lj);
 int64_t apo_factor(const apo_config* c, const double* X, double* L, int64_t* bad_pivot);
 void apo_block_solve(const double* Lj, int64_t len, int32_t l, const double* RI, double* delta);
 void apo_apply_update(const apo_config* c, const double* X, double* R, int64_t blk,
                       const double* delta);
+void apo_update_block(const apo_config* c, const double* X, const double* Lj, double* W,
+                      double* R, int64_t blk, double* delta_out);
 void apo_update(const apo_config* c, const double* X, const double* L, double* W, double* R,
                 int64_t blk, double* delta_out);
 void apo_block_norms(const apo_config* c, const double* R, double* out);

@@ -57,11 +57,14 @@ def _load():
         I64, I32, D = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
         C = ctypes.POINTER(_Cfg)
         sig = {
+            "apo_num_threads": (I32, []),
             "apo_kernel": (D, [C, P, P]),
             "apo_khat_block": (None, [C, P, I64, I64, I64, I64, P]),
             "apo_num_blocks": (I64, [C]),
             "apo_cholesky": (I64, [P, I64]),
             "apo_factor": (I64, [C, P, P, P]),
+            "apo_factor_one": (I64, [C, P, I64, P]),
+            "apo_update_block": (None, [C, P, P, P, P, I64, P]),
             "apo_block_solve": (None, [P, I64, I32, P, P]),
             "apo_apply_update": (None, [C, P, P, I64, P]),
             "apo_update": (None, [C, P, P, P, P, I64, P]),
@@ -149,6 +152,10 @@ class NotPositiveDefinite(RuntimeError):
         self.block, self.pivot = block, pivot
 
 
+def num_threads() -> int:
+    return int(_load().apo_num_threads())
+
+
 def kernel(p: Problem, x, y) -> float:
     x, y = _f64(x), _f64(y)
     c = p.cfg()
@@ -183,6 +190,28 @@ def factor(p: Problem) -> np.ndarray:
     if bad >= 0:
         raise NotPositiveDefinite(bad, piv.value)
     return L
+
+
+def factor_one(p: Problem, j: int) -> np.ndarray:
+    """Cholesky factor of the single block K^_{I_j,I_j} (len_j x len_j)."""
+    s = p.block(j)
+    ln = s.stop - s.start
+    Lj = np.zeros((ln, ln))
+    c = p.cfg()
+    piv = _load().apo_factor_one(ctypes.byref(c), _p(p.X), j, _p(Lj))
+    if piv >= 0:
+        raise NotPositiveDefinite(j, piv)
+    return Lj
+
+
+def update_block(p: Problem, Lj: np.ndarray, W: np.ndarray, R: np.ndarray, blk: int) -> np.ndarray:
+    """One AP update in place given block blk's own factor; returns the step."""
+    s = p.block(blk)
+    delta = np.empty((s.stop - s.start, p.l))
+    c = p.cfg()
+    _load().apo_update_block(ctypes.byref(c), _p(p.X), _p(_f64(Lj)), _p(W), _p(R), blk,
+                             _p(delta))
+    return delta
 
 
 def block_factor(L: np.ndarray, p: Problem, j: int) -> np.ndarray:

@@ -1,0 +1,350 @@
+// C ABI of the alternating-projection solver (declared in include/ap.h):
+// argument validation, workspace layout, launch sequencing and status codes.
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/ap.h"
+#include "ap_internal.h"
+
+struct ap_problem {
+  ap::Layout L;
+  ap::Dev D;
+  ap::Params P;
+  ap_config cfg;  // copy; cfg.lengthscale is not kept
+  const float* X;
+  void* ws;
+  int device;
+  hipEvent_t ev[4];
+  // per-phase event pairs (ap_profile): solve, update, select, check, refine
+  bool prof = false;
+  std::vector<hipEvent_t> pool[5];
+  size_t used[5] = {0, 0, 0, 0, 0};
+};
+
+namespace {
+
+ap_status hip_fail(hipError_t e) { return e == hipSuccess ? AP_OK : AP_ERR_HIP; }
+
+#define AP_HIP(call)                         \
+  do {                                       \
+    hipError_t e_ = (call);                  \
+    if (e_ != hipSuccess) return AP_ERR_HIP; \
+  } while (0)
+
+// Checks every scalar field of the configuration. Returns AP_OK,
+// AP_ERR_INVALID_ARG (out of the method's domain) or AP_ERR_UNSUPPORTED
+// (inside the domain, outside this build's limits).
+ap_status check_config(const ap_config* c) {
+  if (!c || !c->lengthscale) return AP_ERR_INVALID_ARG;
+  if (c->n < 1 || c->d < 1 || c->l < 1 || c->b < 1 || c->b > c->n) return AP_ERR_INVALID_ARG;
+  if (c->kernel < AP_RBF || c->kernel > AP_MATERN52) return AP_ERR_INVALID_ARG;
+  if (c->order != AP_CYCLIC && c->order != AP_GREEDY) return AP_ERR_INVALID_ARG;
+  if (c->tile != AP_TILE_FP32 && c->tile != AP_TILE_BF16) return AP_ERR_INVALID_ARG;
+  if (!(c->outputscale > 0.0) || !std::isfinite(c->outputscale)) return AP_ERR_INVALID_ARG;
+  if (!(c->noise >= 0.0) || !std::isfinite(c->noise)) return AP_ERR_INVALID_ARG;
+  if (!(c->tol >= 0.0) || std::isnan(c->tol)) return AP_ERR_INVALID_ARG;
+  if (c->min_epochs < 0 || c->max_epochs < 1 || c->refine_every < 0) return AP_ERR_INVALID_ARG;
+  for (int k = 0; k < c->d && k < ap::kMaxD; ++k)
+    if (!(c->lengthscale[k] > 0.0) || !std::isfinite(c->lengthscale[k])) return AP_ERR_INVALID_ARG;
+  if (c->d > ap::kMaxD || c->l > ap::kMaxL || c->b > 4096 || c->n >= (int64_t(1) << 31))
+    return AP_ERR_UNSUPPORTED;
+  return AP_OK;
+}
+
+bool valid_handle(const ap_problem* h) { return h != nullptr && h->ws != nullptr; }
+
+bool valid_state(const ap_state* st) { return st && st->B && st->W && st->R; }
+
+ap_status read_ctl(ap_problem* h, hipStream_t s, ap::Ctl* out) {
+  AP_HIP(hipMemcpyAsync(out, h->D.ctl, sizeof(ap::Ctl), hipMemcpyDeviceToHost, s));
+  AP_HIP(hipStreamSynchronize(s));
+  return AP_OK;
+}
+
+enum Phase { kSolve = 0, kUpdate = 1, kSelect = 2, kCheck = 3, kRefine = 4 };
+
+// Records one event of a begin/end pair for `phase` when profiling is on.
+hipError_t mark(ap_problem* h, int phase, hipStream_t s) {
+  if (!h->prof) return hipSuccess;
+  std::vector<hipEvent_t>& pool = h->pool[phase];
+  if (h->used[phase] == pool.size()) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    pool.push_back(e);
+  }
+  return hipEventRecord(pool[h->used[phase]++], s);
+}
+
+#define AP_PHASE(phase, call)                  \
+  do {                                         \
+    AP_HIP(mark(h, phase, s));                 \
+    AP_HIP(call);                              \
+    AP_HIP(mark(h, phase, s));                 \
+  } while (0)
+
+// One block update (inner loop of Algorithm 1). block < 0: greedy selection,
+// whose index is already in the control block.
+ap_status one_update(ap_problem* h, const ap_state* st, int32_t block, bool last,
+                     hipStream_t s) {
+  const bool greedy = h->L.order == AP_GREEDY;
+  AP_PHASE(kSolve, ap::launch_block_solve(h->L, h->D, h->P, block, st->R, st->W, s));
+  AP_PHASE(kUpdate, ap::launch_fused_update(h->L, h->D, block, st->R, greedy, last, s));
+  if (greedy) AP_PHASE(kSelect, ap::launch_select(h->L, h->D, s));
+  return AP_OK;
+}
+
+ap_status refine(ap_problem* h, const ap_state* st, hipStream_t s) {
+  AP_PHASE(kRefine, ap::launch_residual(h->L, h->D, h->P, h->X, st->B, st->W, st->R, true, s));
+  if (h->L.order == AP_GREEDY) AP_PHASE(kSelect, ap::launch_select(h->L, h->D, s));
+  return AP_OK;
+}
+
+ap_status run_epoch(ap_problem* h, const ap_state* st, hipStream_t s) {
+  const bool greedy = h->L.order == AP_GREEDY;
+  for (int32_t u = 0; u < h->L.m; ++u) {
+    ap_status r = one_update(h, st, greedy ? -1 : u, u == h->L.m - 1, s);
+    if (r != AP_OK) return r;
+  }
+  AP_PHASE(kCheck, ap::launch_epoch_check(h->L, h->D, s));
+  return AP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ap_workspace_bytes(const ap_config* cfg) {
+  if (check_config(cfg) != AP_OK) return 0;
+  ap::Layout L;
+  if (!ap::make_layout(cfg->n, cfg->d, cfg->l, cfg->b, cfg->kernel, cfg->order, cfg->tile, &L))
+    return 0;
+  return L.total;
+}
+
+ap_status ap_factor_blocks(const ap_config* cfg, const float* X, void* ws, size_t ws_bytes,
+                           hipStream_t stream, ap_handle* out, int64_t* bad_block) {
+  ap_status cs = check_config(cfg);
+  if (cs != AP_OK) return cs;
+  if (!X || !ws || !out) return AP_ERR_INVALID_ARG;
+  if (((uintptr_t)ws & 255) != 0) return AP_ERR_INVALID_ARG;
+  ap::Layout L;
+  if (!ap::make_layout(cfg->n, cfg->d, cfg->l, cfg->b, cfg->kernel, cfg->order, cfg->tile, &L))
+    return AP_ERR_UNSUPPORTED;
+  if (ws_bytes < L.total) return AP_ERR_WORKSPACE;
+  ap_problem* h = new (std::nothrow) ap_problem();
+  if (!h) return AP_ERR_HIP;
+  h->L = L;
+  h->D = ap::bind(L, ws);
+  h->cfg = *cfg;
+  h->cfg.lengthscale = nullptr;
+  h->X = X;
+  h->ws = ws;
+  for (int k = 0; k < ap::kMaxD; ++k) h->P.ell[k] = k < cfg->d ? cfg->lengthscale[k] : 1.0;
+  h->P.s = cfg->outputscale;
+  h->P.noise = cfg->noise;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    delete h;
+    return AP_ERR_HIP;
+  }
+  for (int i = 0; i < 4; ++i) {
+    if (hipEventCreate(&h->ev[i]) != hipSuccess) {
+      for (int k = 0; k < i; ++k) (void)hipEventDestroy(h->ev[k]);
+      delete h;
+      return AP_ERR_HIP;
+    }
+  }
+  ap_status r = AP_OK;
+  ap::Ctl ctl;
+  if (ap::launch_prep(L, h->D, h->P, X, stream) != hipSuccess ||
+      ap::launch_factor(L, h->D, h->P, X, stream) != hipSuccess) {
+    r = AP_ERR_HIP;
+  } else {
+    r = read_ctl(h, stream, &ctl);
+  }
+  if (r == AP_OK && ctl.fail != ~0ull) {
+    if (bad_block) *bad_block = (int64_t)(ctl.fail >> 32);
+    r = AP_ERR_NOT_PD;
+  }
+  if (r != AP_OK) {
+    ap_destroy(h);
+    return r;
+  }
+  *out = h;
+  return AP_OK;
+}
+
+ap_status ap_reset(ap_handle h, const ap_state* st, hipStream_t stream) {
+  if (!valid_handle(h) || !valid_state(st)) return AP_ERR_INVALID_ARG;
+  return hip_fail(ap::launch_reset(h->L, h->D, st->B, st->W, st->R, stream));
+}
+
+ap_status ap_epoch(const ap_handle* h, const ap_state* st, int32_t count, int32_t epochs,
+                   hipStream_t stream) {
+  if (!h || !st || count < 1 || epochs < 0) return AP_ERR_INVALID_ARG;
+  for (int32_t p = 0; p < count; ++p)
+    if (!valid_handle(h[p]) || !valid_state(&st[p])) return AP_ERR_INVALID_ARG;
+  for (int32_t e = 0; e < epochs; ++e)
+    for (int32_t p = 0; p < count; ++p) {
+      ap_status r = run_epoch(h[p], &st[p], stream);
+      if (r != AP_OK) return r;
+    }
+  return AP_OK;
+}
+
+ap_status ap_update(ap_handle h, const ap_state* st, int32_t block, hipStream_t stream) {
+  if (!valid_handle(h) || !valid_state(st)) return AP_ERR_INVALID_ARG;
+  if (block < 0 || block >= h->L.m) return AP_ERR_INVALID_ARG;
+  return one_update(h, st, block, true, stream);
+}
+
+ap_status ap_rel_residual(ap_handle h, hipStream_t stream, double* rho, double* col_ratio) {
+  if (!valid_handle(h) || !rho) return AP_ERR_INVALID_ARG;
+  ap::Ctl c;
+  ap_status r = read_ctl(h, stream, &c);
+  if (r != AP_OK) return r;
+  if (c.status != 0 || !std::isfinite(c.rho)) return AP_ERR_NONFINITE;
+  *rho = c.rho;
+  if (col_ratio)
+    for (int i = 0; i < h->L.l; ++i) col_ratio[i] = c.colrel[i];
+  return AP_OK;
+}
+
+ap_status ap_residual(ap_handle h, const ap_state* st, float* R_out, double* col_rel,
+                      hipStream_t stream) {
+  if (!valid_handle(h) || !valid_state(st)) return AP_ERR_INVALID_ARG;
+  const bool in_place = R_out == nullptr || R_out == st->R;
+  if (in_place) {
+    ap_status r = refine(h, st, stream);
+    if (r != AP_OK) return r;
+  } else {
+    hipStream_t s = stream;
+    AP_PHASE(kRefine, ap::launch_residual(h->L, h->D, h->P, h->X, st->B, st->W, R_out, false, s));
+  }
+  if (col_rel) {
+    ap::Ctl c;
+    ap_status r = read_ctl(h, stream, &c);
+    if (r != AP_OK) return r;
+    if (c.status != 0) return AP_ERR_NONFINITE;
+    for (int i = 0; i < h->L.l; ++i) col_rel[i] = c.colrel_true[i];
+  }
+  return AP_OK;
+}
+
+ap_status ap_solve(ap_handle h, const ap_state* st, hipStream_t stream, ap_stats* out) {
+  if (!valid_handle(h) || !valid_state(st)) return AP_ERR_INVALID_ARG;
+  const ap_config& c = h->cfg;
+  ap_stats s{};
+  s.rho_true = NAN;
+  ap_status r = ap_reset(h, st, stream);
+  if (r != AP_OK) return r;
+  const bool confirm = c.refine_every > 0 || c.tile == AP_TILE_BF16;
+  ap_status result = AP_NOT_CONVERGED;
+  ap::Ctl ctl;
+  double t_ep = 0.0, t_ref = 0.0;
+  for (int32_t t = 1; t <= c.max_epochs; ++t) {
+    AP_HIP(hipEventRecord(h->ev[0], stream));
+    r = run_epoch(h, st, stream);
+    if (r != AP_OK) return r;
+    AP_HIP(hipEventRecord(h->ev[1], stream));
+    bool refined = false;
+    if (c.refine_every > 0 && t % c.refine_every == 0) {
+      r = refine(h, st, stream);
+      if (r != AP_OK) return r;
+      refined = true;
+      s.refines++;
+    }
+    AP_HIP(hipEventRecord(h->ev[2], stream));
+    r = read_ctl(h, stream, &ctl);
+    if (r != AP_OK) return r;
+    float ms = 0.f;
+    AP_HIP(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
+    t_ep += ms * 1e-3;
+    AP_HIP(hipEventElapsedTime(&ms, h->ev[1], h->ev[2]));
+    t_ref += ms * 1e-3;
+    if (ctl.status != 0 || !std::isfinite(ctl.rho)) return AP_ERR_NONFINITE;
+    s.epochs = t;
+    s.rho_maintained = ctl.rho;
+    double rho = refined ? ctl.rho_true : ctl.rho;
+    if (refined) s.rho_true = ctl.rho_true;
+    if (rho < c.tol && t >= c.min_epochs) {
+      if (confirm && !refined) {
+        AP_HIP(hipEventRecord(h->ev[1], stream));
+        r = refine(h, st, stream);
+        if (r != AP_OK) return r;
+        AP_HIP(hipEventRecord(h->ev[2], stream));
+        r = read_ctl(h, stream, &ctl);
+        if (r != AP_OK) return r;
+        AP_HIP(hipEventElapsedTime(&ms, h->ev[1], h->ev[2]));
+        t_ref += ms * 1e-3;
+        s.refines++;
+        s.rho_true = ctl.rho_true;
+        if (ctl.status != 0) return AP_ERR_NONFINITE;
+        if (!(ctl.rho_true < c.tol)) continue;  // the true residual says go on
+      }
+      result = AP_OK;
+      break;
+    }
+  }
+  s.t_epochs = t_ep;
+  s.t_refine = t_ref;
+  if (out) *out = s;
+  return result;
+}
+
+ap_status ap_block_inverse(ap_handle h, int32_t j, double* dst, hipStream_t stream) {
+  if (!valid_handle(h) || !dst || j < 0 || j >= h->L.m) return AP_ERR_INVALID_ARG;
+  return hip_fail(ap::launch_copy_inverse(h->L, h->D, j, dst, stream));
+}
+
+ap_status ap_profile(ap_handle h, int32_t enable) {
+  if (!valid_handle(h)) return AP_ERR_INVALID_ARG;
+  h->prof = enable != 0;
+  for (int p = 0; p < 5; ++p) h->used[p] = 0;
+  return AP_OK;
+}
+
+ap_status ap_profile_read(ap_handle h, hipStream_t stream, double* seconds, int64_t* launches) {
+  if (!valid_handle(h) || !seconds || !launches) return AP_ERR_INVALID_ARG;
+  AP_HIP(hipStreamSynchronize(stream));
+  for (int p = 0; p < 5; ++p) {
+    double tot = 0.0;
+    for (size_t i = 0; i + 1 < h->used[p]; i += 2) {
+      float ms = 0.f;
+      AP_HIP(hipEventElapsedTime(&ms, h->pool[p][i], h->pool[p][i + 1]));
+      tot += ms * 1e-3;
+    }
+    seconds[p] = tot;
+    launches[p] = (int64_t)(h->used[p] / 2);
+  }
+  return AP_OK;
+}
+
+void ap_destroy(ap_handle h) {
+  if (!h) return;
+  for (int i = 0; i < 4; ++i)
+    if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
+  for (int p = 0; p < 5; ++p)
+    for (hipEvent_t e : h->pool[p]) (void)hipEventDestroy(e);
+  delete h;
+}
+
+const char* ap_status_str(ap_status s) {
+  switch (s) {
+    case AP_OK: return "ok";
+    case AP_NOT_CONVERGED: return "not converged within max_epochs";
+    case AP_ERR_INVALID_ARG: return "invalid argument";
+    case AP_ERR_NOT_PD: return "a diagonal block is not positive definite";
+    case AP_ERR_NONFINITE: return "non-finite residual";
+    case AP_ERR_WORKSPACE: return "workspace too small";
+    case AP_ERR_HIP: return "HIP runtime error";
+    case AP_ERR_UNSUPPORTED: return "size not supported by this build";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,108 @@
+// Internal declarations shared by the host library and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace ap {
+
+// Rows of the residual handled by one workgroup of the fused update: 4 waves,
+// each owning two 32-row MFMA tiles.
+constexpr int kRowsWG = 256;
+// Block columns consumed per step of the fused update's inner loop.
+constexpr int kChunk = 32;
+// Right-hand sides handled by one pass (the M dimension of the 32x32 MFMA).
+constexpr int kMaxL = 32;
+// FP64 tile edge of the batched factorization.
+constexpr int kT = 64;
+// K-split of the FP64 block solve.
+constexpr int kBsSplit = 16;
+// Rows per workgroup of the FP64 true residual.
+constexpr int kResRows = 64;
+constexpr int kMaxD = 20;
+
+// Device control block at the start of the workspace.
+struct Ctl {
+  unsigned long long fail;  // first non-positive pivot: (block << 32) | pivot, ~0 if none
+  int32_t status;           // 0 ok, else an ap_status (non-finite residual)
+  int32_t sel;              // selected block of the next update (greedy order)
+  int32_t epoch;            // epochs completed since the last reset
+  int32_t pad0;
+  double rho;               // mean column ratio after the last epoch
+  double rho_true;          // the same for the last FP64 true residual
+  double bnorm2[kMaxL];     // ||B_c||^2
+  double colrel[kMaxL];     // ||R_c|| / ||B_c|| after the last epoch
+  double colrel_true[kMaxL];
+  double mu[kMaxD];         // feature centre used by the prepared copies
+};
+
+// Kernel map constants. The prepared features v = (x - mu) / ell * c_feat make
+// the map a function of |v_i - v_j|^2 only:
+//  RBF:        k/s = exp2(-|dv|^2)                      (c_feat = sqrt(log2(e) / 2))
+//  Matern-3/2: t = |dv| ; k/s = (1 + t / log2 e) exp2(-t)         (c_feat = sqrt3 log2 e)
+//  Matern-5/2: t = |dv| ; k/s = (1 + t / log2 e + t^2 / (3 log2^2 e)) exp2(-t)
+//                                                                   (c_feat = sqrt5 log2 e)
+constexpr double kLog2e = 1.4426950408889634;
+
+struct Layout {
+  int64_t n, n_pad;      // n_pad >= n + 32, multiple of kRowsWG
+  int32_t d, l, b, m, b_pad, last_len;
+  int32_t kernel, order, tile;
+  int32_t ks;            // BF16 K-steps of 16 feature slots (3d + 6 slots)
+  int32_t dp;            // FP32 feature stride (d rounded up to 4)
+  int32_t nwg;           // workgroups of the fused update: n_pad / kRowsWG
+  int32_t nwg_res;       // workgroups of the true residual
+  size_t off_ctl, off_xs, off_xrow, off_xcol, off_kinv, off_dinv, off_panel, off_delta,
+      off_bspart, off_dtile, off_rowsq, off_colsq, off_blocknorm, off_respart, off_mupart;
+  size_t total;
+};
+
+struct Dev {  // device pointers into one problem's workspace
+  Ctl* ctl;
+  float* xs;             // FP32 path: n_pad x dp
+  uint16_t* xrow;        // BF16 path: n_pad x 16 ks (row-role operand)
+  uint16_t* xcol;        // BF16 path: n_pad x 16 ks (column-role operand)
+  double* kinv;          // m x b_pad x b_pad
+  double* dinv;          // factor scratch: m x (b_pad/64) x 64 x 64
+  double* panel;         // factor scratch: m x (b_pad/64) x 64 x 64
+  double* delta;         // b_pad x 32 FP64 block step
+  double* bspart;        // kBsSplit x b_pad x 32 partial products
+  void* dtile;           // block step as the fused update's MFMA operand
+  float* rowsq;          // n_pad per-row sums of squares of R (greedy order)
+  float* colsq;          // nwg x 32 per-workgroup column sums of squares
+  double* blocknorm;     // m block norms ||R_I||_F^2
+  double* respart;       // nwg_res x 32 FP64 column partials of the true residual
+  double* mupart;        // feature-centre partial sums
+};
+
+struct Params {  // hyperparameters as the kernels need them
+  double ell[kMaxD];
+  double s, noise;
+};
+
+bool make_layout(int64_t n, int32_t d, int32_t l, int32_t b, int32_t kernel, int32_t order,
+                 int32_t tile, Layout* L);
+Dev bind(const Layout& L, void* ws);
+
+// ---- launchers (each enqueues on `st` and returns the launch status) -------
+hipError_t launch_prep(const Layout& L, const Dev& D, const Params& P, const float* X,
+                       hipStream_t st);
+hipError_t launch_factor(const Layout& L, const Dev& D, const Params& P, const float* X,
+                         hipStream_t st);
+hipError_t launch_reset(const Layout& L, const Dev& D, const float* B, double* W, float* R,
+                        hipStream_t st);
+// block < 0: read the block index from ctl->sel (greedy order)
+hipError_t launch_block_solve(const Layout& L, const Dev& D, const Params& P, int32_t block,
+                              const float* R, double* W, hipStream_t st);
+hipError_t launch_fused_update(const Layout& L, const Dev& D, int32_t block, float* R,
+                               bool want_rowsq, bool want_colsq, hipStream_t st);
+hipError_t launch_select(const Layout& L, const Dev& D, hipStream_t st);
+hipError_t launch_epoch_check(const Layout& L, const Dev& D, hipStream_t st);
+hipError_t launch_residual(const Layout& L, const Dev& D, const Params& P, const float* X,
+                           const float* B, const double* W, float* Rout, bool in_place,
+                           hipStream_t st);
+hipError_t launch_copy_inverse(const Layout& L, const Dev& D, int32_t j, double* dst,
+                               hipStream_t st);
+
+}  // namespace ap

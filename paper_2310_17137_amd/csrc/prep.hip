@@ -1,0 +1,374 @@
+// Workspace layout, feature preparation, Algorithm 1's initialization, block
+// selection and the epoch-end residual check.
+#include <algorithm>
+#include <cmath>
+
+#include "ap_internal.h"
+
+namespace ap {
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool make_layout(int64_t n, int32_t d, int32_t l, int32_t b, int32_t kernel, int32_t order,
+                 int32_t tile, Layout* L) {
+  if (n < 1 || d < 1 || d > kMaxD || l < 1 || l > kMaxL || b < 1 || b > 4096 || b > n ||
+      n >= (int64_t(1) << 31))
+    return false;
+  Layout o{};
+  o.n = n;
+  o.d = d;
+  o.l = l;
+  o.b = b;
+  o.m = (int32_t)((n + b - 1) / b);
+  o.b_pad = (b + kT - 1) / kT * kT;
+  o.last_len = (int32_t)(n - (int64_t)(o.m - 1) * b);
+  o.kernel = kernel;
+  o.order = order;
+  o.tile = tile;
+  o.ks = (3 * d + 6 + 15) / 16;
+  o.dp = (d + 3) / 4 * 4;
+  o.n_pad = (n + 32 + kRowsWG - 1) / kRowsWG * kRowsWG;
+  o.nwg = (int32_t)(o.n_pad / kRowsWG);
+  o.nwg_res = (int32_t)((n + kResRows - 1) / kResRows);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off = align256(off + bytes);
+    return at;
+  };
+  o.off_ctl = take(sizeof(Ctl));
+  o.off_xs = take(tile == 0 ? (size_t)o.n_pad * 2 * o.dp * sizeof(float) : 0);
+  o.off_xrow = take(tile == 1 ? (size_t)o.n_pad * 16 * o.ks * 2 : 0);
+  o.off_xcol = take(tile == 1 ? (size_t)o.n_pad * 16 * o.ks * 2 : 0);
+  o.off_kinv = take((size_t)o.m * o.b_pad * o.b_pad * sizeof(double));
+  o.off_dinv = take((size_t)o.m * o.b_pad * kT * sizeof(double));
+  o.off_panel = take((size_t)o.m * o.b_pad * kT * sizeof(double));
+  o.off_delta = take((size_t)o.b_pad * kMaxL * sizeof(double));
+  o.off_bspart = take((size_t)kBsSplit * o.b_pad * kMaxL * sizeof(double));
+  o.off_dtile = take((size_t)o.b_pad * kMaxL * sizeof(float));
+  o.off_rowsq = take((size_t)o.n_pad * sizeof(float));
+  o.off_colsq = take((size_t)o.nwg * kMaxL * sizeof(float));
+  o.off_blocknorm = take((size_t)o.m * sizeof(double));
+  o.off_respart = take((size_t)std::max(o.nwg_res, 1024) * kMaxL * sizeof(double));
+  o.off_mupart = take((size_t)256 * kMaxD * sizeof(double));
+  o.total = off;
+  *L = o;
+  return true;
+}
+
+Dev bind(const Layout& L, void* ws) {
+  char* base = (char*)ws;
+  Dev D;
+  D.ctl = (Ctl*)(base + L.off_ctl);
+  D.xs = (float*)(base + L.off_xs);
+  D.xrow = (uint16_t*)(base + L.off_xrow);
+  D.xcol = (uint16_t*)(base + L.off_xcol);
+  D.kinv = (double*)(base + L.off_kinv);
+  D.dinv = (double*)(base + L.off_dinv);
+  D.panel = (double*)(base + L.off_panel);
+  D.delta = (double*)(base + L.off_delta);
+  D.bspart = (double*)(base + L.off_bspart);
+  D.dtile = (void*)(base + L.off_dtile);
+  D.rowsq = (float*)(base + L.off_rowsq);
+  D.colsq = (float*)(base + L.off_colsq);
+  D.blocknorm = (double*)(base + L.off_blocknorm);
+  D.respart = (double*)(base + L.off_respart);
+  D.mupart = (double*)(base + L.off_mupart);
+  return D;
+}
+
+namespace {
+
+// Round to nearest even BF16 (finite inputs).
+__device__ inline uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ inline double feat_scale(int kernel) {
+  if (kernel == 0) return sqrt(0.5 * kLog2e);
+  if (kernel == 1) return 1.7320508075688772 * kLog2e;
+  return 2.23606797749979 * kLog2e;
+}
+
+// Column sums of X in FP64: 256 workgroups, one strided slice each.
+__global__ __launch_bounds__(256) void k_mu_partial(Layout L, const float* __restrict__ X,
+                                                    double* __restrict__ part) {
+  __shared__ double red[256];
+  for (int k = 0; k < L.d; ++k) {
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < L.n; i += 256 * 256)
+      acc += (double)X[i * L.d + k];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x * kMaxD + k] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ void k_mu_final(Layout L, const double* __restrict__ part, Ctl* ctl) {
+  int k = threadIdx.x;
+  if (k < L.d) {
+    double acc = 0.0;
+    for (int g = 0; g < 256; ++g) acc += part[g * kMaxD + k];
+    ctl->mu[k] = acc / (double)L.n;
+  }
+  if (k == 0) {
+    ctl->fail = ~0ull;
+    ctl->status = 0;
+    ctl->sel = 0;
+    ctl->epoch = 0;
+    ctl->rho = 0.0;
+    ctl->rho_true = 0.0;
+  }
+}
+
+// Prepared copies of the features, v = (x - mu) / ell * c (one thread per row).
+// FP32 path: xs[i] = [vh, vl], two FP32 terms with v = vh + vl to 2^-48, so a
+// difference of two points is formed without the rounding of v itself. BF16 path: v = vh + vl (two BF16 terms), |v|^2 = nh + nm + nl
+// (three BF16 terms), and the row / column operands
+//   row: [vh, vh, vl, -nh, -nm, -nl, 1, 1, 1, 0...]
+//   col: [2vh, 2vl, 2vh, 1, 1, 1, -nh, -nm, -nl, 0...]
+// whose dot product is 2 v_i.v_j - |v_i|^2 - |v_j|^2 = -|v_i - v_j|^2 (the
+// vl_i.vl_j term dropped). Padding rows (i >= n) are zero.
+__global__ __launch_bounds__(256) void k_prep(Layout L, Params P, const float* __restrict__ X,
+                                              const Ctl* __restrict__ ctl, float* __restrict__ xs,
+                                              uint16_t* __restrict__ xrow,
+                                              uint16_t* __restrict__ xcol) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= L.n_pad) return;
+  const double c = feat_scale(L.kernel);
+  const int d = L.d;
+  if (L.tile == 0) {
+    for (int k = 0; k < L.dp; ++k) {
+      float vh = 0.f, vl = 0.f;
+      if (i < L.n && k < d) {
+        double v = ((double)X[i * d + k] - ctl->mu[k]) / P.ell[k] * c;
+        vh = (float)v;
+        vl = (float)(v - (double)vh);
+      }
+      xs[i * 2 * L.dp + k] = vh;
+      xs[i * 2 * L.dp + L.dp + k] = vl;
+    }
+    return;
+  }
+  const int kf = 16 * L.ks;
+  uint16_t* r = xrow + i * kf;
+  uint16_t* q = xcol + i * kf;
+  for (int k = 0; k < kf; ++k) {
+    r[k] = 0;
+    q[k] = 0;
+  }
+  if (i >= L.n) return;
+  const uint16_t one = to_bf16(1.0f);
+  double nrm = 0.0;
+  for (int k = 0; k < d; ++k) {
+    double v = ((double)X[i * d + k] - ctl->mu[k]) / P.ell[k] * c;
+    uint16_t hi = to_bf16((float)v);
+    double vh = (double)from_bf16(hi);
+    uint16_t lo = to_bf16((float)(v - vh));
+    double vl = (double)from_bf16(lo);
+    double vv = vh + vl;
+    nrm += vv * vv;
+    uint16_t hi2 = to_bf16(2.0f * from_bf16(hi));
+    uint16_t lo2 = to_bf16(2.0f * from_bf16(lo));
+    r[k] = hi;
+    r[d + k] = hi;
+    r[2 * d + k] = lo;
+    q[k] = hi2;
+    q[d + k] = lo2;
+    q[2 * d + k] = hi2;
+  }
+  uint16_t nh = to_bf16((float)nrm);
+  double rem = nrm - (double)from_bf16(nh);
+  uint16_t nm = to_bf16((float)rem);
+  rem -= (double)from_bf16(nm);
+  uint16_t nl = to_bf16((float)rem);
+  const int o = 3 * d;
+  r[o + 0] = nh ^ 0x8000;
+  r[o + 1] = nm ^ 0x8000;
+  r[o + 2] = nl ^ 0x8000;
+  r[o + 3] = one;
+  r[o + 4] = one;
+  r[o + 5] = one;
+  q[o + 0] = one;
+  q[o + 1] = one;
+  q[o + 2] = one;
+  q[o + 3] = nh ^ 0x8000;
+  q[o + 4] = nm ^ 0x8000;
+  q[o + 5] = nl ^ 0x8000;
+}
+
+// W = 0, R = B (Algorithm 1 initialization), per-row sums of squares of B, and
+// per-workgroup FP64 column partials of ||B_c||^2.
+__global__ __launch_bounds__(256) void k_reset(Layout L, const float* __restrict__ B,
+                                               double* __restrict__ W, float* __restrict__ R,
+                                               float* __restrict__ rowsq,
+                                               double* __restrict__ part) {
+  __shared__ double red[256 * 2];
+  const int l = L.l;
+  double col[kMaxL];
+  for (int c = 0; c < kMaxL; ++c) col[c] = 0.0;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < L.n_pad; i += (int64_t)gridDim.x * 256) {
+    float rs = 0.f;
+    if (i < L.n) {
+      for (int c = 0; c < l; ++c) {
+        float v = B[i * l + c];
+        R[i * l + c] = v;
+        W[i * l + c] = 0.0;
+        rs = fmaf(v, v, rs);
+        col[c] += (double)v * (double)v;
+      }
+    }
+    rowsq[i] = rs;
+  }
+  for (int c = 0; c < l; ++c) {
+    red[threadIdx.x] = col[c];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x * kMaxL + c] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ void k_reset_final(Layout L, const double* __restrict__ part, int groups, Ctl* ctl) {
+  int c = threadIdx.x;
+  if (c < L.l) {
+    double acc = 0.0;
+    for (int g = 0; g < groups; ++g) acc += part[g * kMaxL + c];
+    ctl->bnorm2[c] = acc;
+  }
+  if (c == 0) {
+    ctl->status = 0;
+    ctl->sel = 0;
+    ctl->epoch = 0;
+    ctl->rho = 1.0;
+  }
+}
+
+// ||R_I||_F^2 for every block from the per-row sums of squares (one workgroup
+// per block, fixed reduction order).
+__global__ __launch_bounds__(256) void k_block_norms(Layout L, const float* __restrict__ rowsq,
+                                                     double* __restrict__ out) {
+  __shared__ double red[256];
+  const int64_t j = blockIdx.x;
+  const int64_t s = j * L.b;
+  const int64_t e = std::min<int64_t>(s + L.b, L.n);
+  double acc = 0.0;
+  for (int64_t i = s + threadIdx.x; i < e; i += 256) acc += (double)rowsq[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = red[0];
+}
+
+// Modified Gauss-Southwell rule: argmax over blocks, ties to the lowest index.
+__global__ __launch_bounds__(256) void k_argmax(Layout L, const double* __restrict__ nrm,
+                                                Ctl* ctl) {
+  __shared__ double bv[256];
+  __shared__ int bi[256];
+  double best = -1.0;
+  int idx = 0x7fffffff;
+  for (int j = threadIdx.x; j < L.m; j += 256) {
+    double v = nrm[j];
+    if (v > best) {
+      best = v;
+      idx = j;
+    }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = idx;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      double v2 = bv[threadIdx.x + s];
+      int i2 = bi[threadIdx.x + s];
+      if (v2 > bv[threadIdx.x] || (v2 == bv[threadIdx.x] && i2 < bi[threadIdx.x])) {
+        bv[threadIdx.x] = v2;
+        bi[threadIdx.x] = i2;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) ctl->sel = bi[0];
+}
+
+// Epoch-end check (Section 5, "Alternating Projection Details"): column norms
+// of R from the fused update's per-workgroup partials, in a fixed order, then
+// rho = mean_c ||r_c|| / ||b_c||.
+__global__ __launch_bounds__(256) void k_epoch_check(Layout L, const float* __restrict__ colsq,
+                                                     Ctl* ctl) {
+  __shared__ double red[256];
+  __shared__ double ratio[kMaxL];
+  for (int c = 0; c < L.l; ++c) {
+    double acc = 0.0;
+    for (int g = threadIdx.x; g < L.nwg; g += 256) acc += (double)colsq[g * kMaxL + c];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      double bn = ctl->bnorm2[c];
+      double r = bn > 0.0 ? sqrt(red[0]) / sqrt(bn) : 0.0;
+      if (!isfinite(red[0])) r = NAN;
+      ratio[c] = r;
+      ctl->colrel[c] = r;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double acc = 0.0;
+    for (int c = 0; c < L.l; ++c) acc += ratio[c];
+    double rho = acc / L.l;
+    ctl->rho = rho;
+    ctl->epoch += 1;
+    if (!isfinite(rho)) ctl->status = -3;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_prep(const Layout& L, const Dev& D, const Params& P, const float* X,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_mu_partial, dim3(256), dim3(256), 0, st, L, X, D.mupart);
+  hipLaunchKernelGGL(k_mu_final, dim3(1), dim3(64), 0, st, L, D.mupart, D.ctl);
+  unsigned g = (unsigned)((L.n_pad + 255) / 256);
+  hipLaunchKernelGGL(k_prep, dim3(g), dim3(256), 0, st, L, P, X, D.ctl, D.xs, D.xrow, D.xcol);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset(const Layout& L, const Dev& D, const float* B, double* W, float* R,
+                        hipStream_t st) {
+  const int groups = 1024;
+  hipLaunchKernelGGL(k_reset, dim3(groups), dim3(256), 0, st, L, B, W, R, D.rowsq, D.respart);
+  hipLaunchKernelGGL(k_reset_final, dim3(1), dim3(64), 0, st, L, D.respart, groups, D.ctl);
+  if (L.order == 1) return launch_select(L, D, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_select(const Layout& L, const Dev& D, hipStream_t st) {
+  hipLaunchKernelGGL(k_block_norms, dim3(L.m), dim3(256), 0, st, L, D.rowsq, D.blocknorm);
+  hipLaunchKernelGGL(k_argmax, dim3(1), dim3(256), 0, st, L, D.blocknorm, D.ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_epoch_check(const Layout& L, const Dev& D, hipStream_t st) {
+  hipLaunchKernelGGL(k_epoch_check, dim3(1), dim3(256), 0, st, L, D.colsq, D.ctl);
+  return hipGetLastError();
+}
+
+}  // namespace ap

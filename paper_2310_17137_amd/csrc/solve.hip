@@ -1,0 +1,120 @@
+// FP64 block solve of Algorithm 1's weight update (eq. text_update_of_w):
+//   delta = K^_{I,I}^{-1} R_I,  W_I += delta,
+// with the cached inverse, so the solve is one FP64 product of a b x b matrix
+// with the b x l block of the residual. The step is also written, times the
+// outputscale, in the operand layout of the fused residual update (BF16 or FP32).
+#include <algorithm>
+
+#include "ap_internal.h"
+
+namespace ap {
+namespace {
+
+// Partial products over one of kBsSplit slices of the block columns q.
+// Workgroup: 64 output rows (one per lane) x LB >= l columns; the 4 waves take
+// interleaved quarters of the slice. The inverse is read along rows of its
+// symmetric storage, K^-1[q][i] = K^-1[i][q], so the 64 lanes of a wave read
+// 512 contiguous bytes per q; R_I is staged once per slice in LDS as FP64.
+template <int LB>
+__global__ __launch_bounds__(256) void k_bs_partial(Layout L, const double* __restrict__ kinv,
+                                                    const Ctl* __restrict__ ctl, int block,
+                                                    const float* __restrict__ R,
+                                                    double* __restrict__ part) {
+  constexpr int kSlice = 4096 / kBsSplit;       // largest slice (b_pad <= 4096)
+  __shared__ double smem[kSlice * LB > 4 * 64 * LB ? kSlice * LB : 4 * 64 * LB];
+  const int blk = block >= 0 ? block : ctl->sel;
+  const int64_t start = (int64_t)blk * L.b;
+  const int len = (int)std::min<int64_t>(L.b, L.n - start);
+  const int l = L.l;
+  const int ntile = L.b_pad / 64;
+  const int it = blockIdx.x % ntile, sp = blockIdx.x / ntile;
+  const int slice = L.b_pad / kBsSplit;  // multiple of 4
+  const int q0 = sp * slice;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int i = it * 64 + lane;
+  const double* K = kinv + (size_t)blk * L.b_pad * L.b_pad;
+  for (int e = threadIdx.x; e < slice * LB; e += 256) {
+    int qq = e / LB, c = e % LB;
+    int q = q0 + qq;
+    smem[e] = (q < len && c < l) ? (double)R[(start + q) * l + c] : 0.0;
+  }
+  __syncthreads();
+  double acc[LB];
+#pragma unroll
+  for (int c = 0; c < LB; ++c) acc[c] = 0.0;
+  for (int qq = wave; qq < slice; qq += 4) {
+    const double kv = K[(size_t)(q0 + qq) * L.b_pad + i];
+    const double* rq = smem + qq * LB;
+#pragma unroll
+    for (int c = 0; c < LB; ++c) acc[c] = fma(kv, rq[c], acc[c]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < LB; ++c) smem[(wave * 64 + lane) * LB + c] = acc[c];
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * kMaxL; e += 256) {
+    int r = e / kMaxL, c = e % kMaxL;
+    double v = 0.0;
+    if (c < LB)
+      v = ((smem[(0 * 64 + r) * LB + c] + smem[(1 * 64 + r) * LB + c]) +
+           smem[(2 * 64 + r) * LB + c]) + smem[(3 * 64 + r) * LB + c];
+    part[((size_t)sp * L.b_pad + it * 64 + r) * kMaxL + c] = v;
+  }
+}
+
+// Sum the slices in a fixed order, update W_I, keep delta in FP64 and write
+// s * delta in the fused update's operand layout.
+__global__ __launch_bounds__(256) void k_bs_finish(Layout L, const Ctl* __restrict__ ctl,
+                                                   int block, double s,
+                                                   const double* __restrict__ part,
+                                                   double* __restrict__ W,
+                                                   double* __restrict__ delta, void* dtile) {
+  const int blk = block >= 0 ? block : ctl->sel;
+  const int64_t start = (int64_t)blk * L.b;
+  const int len = (int)std::min<int64_t>(L.b, L.n - start);
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= L.b_pad * kMaxL) return;
+  const int i = e / kMaxL, c = e % kMaxL;
+  double v = 0.0;
+  if (i < len && c < L.l) {
+    for (int sp = 0; sp < kBsSplit; ++sp) v += part[((size_t)sp * L.b_pad + i) * kMaxL + c];
+    W[(start + i) * L.l + c] += v;
+  }
+  delta[i * kMaxL + c] = v;
+  const float sv = (float)(s * v);
+  if (L.tile == 0) {
+    ((float*)dtile)[i * kMaxL + c] = sv;
+  } else {
+    // bcol i of chunk ch: k-step st = w / 16; within it bcol = 4g + (e % 4) + 8 (e / 4)
+    const int ch = i / 32, w = i % 32, st = w / 16, w2 = w % 16;
+    const int g = (w2 % 8) / 4, el = (w2 / 8) * 4 + w2 % 4;
+    const int lane = g * 32 + c;
+    uint32_t u = __float_as_uint(sv);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    ((uint16_t*)dtile)[(((size_t)ch * 2 + st) * 64 + lane) * 8 + el] = (uint16_t)(u >> 16);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_block_solve(const Layout& L, const Dev& D, const Params& P, int32_t block,
+                              const float* R, double* W, hipStream_t st) {
+  const int ntile = L.b_pad / 64;
+  const dim3 g(ntile * kBsSplit), t(256);
+  if (L.l <= 1)
+    hipLaunchKernelGGL(k_bs_partial<1>, g, t, 0, st, L, D.kinv, D.ctl, block, R, D.bspart);
+  else if (L.l <= 4)
+    hipLaunchKernelGGL(k_bs_partial<4>, g, t, 0, st, L, D.kinv, D.ctl, block, R, D.bspart);
+  else if (L.l <= 8)
+    hipLaunchKernelGGL(k_bs_partial<8>, g, t, 0, st, L, D.kinv, D.ctl, block, R, D.bspart);
+  else if (L.l <= 16)
+    hipLaunchKernelGGL(k_bs_partial<16>, g, t, 0, st, L, D.kinv, D.ctl, block, R, D.bspart);
+  else
+    hipLaunchKernelGGL(k_bs_partial<32>, g, t, 0, st, L, D.kinv, D.ctl, block, R, D.bspart);
+  const int tot = L.b_pad * kMaxL;
+  hipLaunchKernelGGL(k_bs_finish, dim3((tot + 255) / 256), dim3(256), 0, st, L, D.ctl, block,
+                     P.s, D.bspart, W, D.delta, D.dtile);
+  return hipGetLastError();
+}
+
+}  // namespace ap

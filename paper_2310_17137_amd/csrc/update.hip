@@ -1,0 +1,308 @@
+// Fused residual update of Algorithm 1 (eq. text_update_of_r):
+//   R <- R - K^_{:,I} delta,   delta = K^_{I,I}^{-1} R_I,
+// with K^_{:,I} evaluated tile by tile from the features and never stored.
+// On the rows of I the update is exactly zero (K^_{I,I} K^_{I,I}^{-1} R_I = R_I),
+// and those rows are written as 0. In the same pass the kernel reduces the new
+// residual's per-row sums of squares (the block norms of the modified
+// Gauss-Southwell rule, eq. approximate_gauss_southwell) and per-workgroup
+// column sums of squares (the epoch-end stopping test).
+//
+// One workgroup = 4 wave64s = 256 rows; a wave owns two 32-row tiles. The block
+// is walked in chunks of 32 columns. Every chunk is a pair of 32 x 32 MFMA
+// products per row tile: S^T = X_chunk X_rows^T (tile x.x' -> kernel map in
+// registers) and acc += delta_chunk^T K_tile^T. Computing the transposed tile
+// makes the first product's accumulator layout (lane = data row, 16 chunk
+// columns) the second product's B operand, so the kernel values go from the
+// map straight into the next MFMA without leaving registers.
+#include <algorithm>
+
+#include "ap_internal.h"
+
+namespace ap {
+namespace {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+typedef __attribute__((ext_vector_type(2))) float f32x2;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+typedef __attribute__((ext_vector_type(16))) double f64x16;
+
+constexpr float kInvLog2e = 0.6931471805599453f;             // 1 / log2(e)
+constexpr float kInv3Log2e2 = 0.16017132519074588f;          // 1 / (3 log2(e)^2)
+
+// Kernel map on the prepared squared distance. `a` is -|v_i - v_j|^2 (BF16
+// path) or |v_i - v_j|^2 (FP32 path); only its magnitude enters the Matern maps.
+template <int KERN>
+__device__ __forceinline__ float kmap_neg(float a) {  // a = -|dv|^2
+  if constexpr (KERN == 0) {
+    return __builtin_amdgcn_exp2f(a);
+  } else {
+    float t = __builtin_amdgcn_sqrtf(fabsf(a));
+    float e = __builtin_amdgcn_exp2f(-t);
+    if constexpr (KERN == 1) return fmaf(t, kInvLog2e, 1.0f) * e;
+    return fmaf(t, fmaf(t, kInv3Log2e2, kInvLog2e), 1.0f) * e;
+  }
+}
+
+__device__ __forceinline__ bf16x8 load_bf16x8(const uint16_t* p) {
+  uint4 u = *reinterpret_cast<const uint4*>(p);
+  return __builtin_bit_cast(bf16x8, u);
+}
+
+__device__ __forceinline__ bf16x8 pack8(const f32x16& v, int base) {
+  bf16x8 r;
+#pragma unroll
+  for (int e = 0; e < 8; e += 2) {
+    f32x2 f = {v[base + e], v[base + e + 1]};
+    bf16x2 h = __builtin_convertvector(f, bf16x2);
+    r[e] = h[0];
+    r[e + 1] = h[1];
+  }
+  return r;
+}
+
+// Epilogue shared by both tile precisions. acc[t][v] holds, for data row
+// row0 + 32 t + lane % 32, the update of column m = 8 (v / 4) + 4 (lane / 32) + v % 4.
+template <typename Acc>
+__device__ __forceinline__ void epilogue(const Layout& L, int64_t row0, int64_t start, int len,
+                                         const Acc acc[2], float* __restrict__ R,
+                                         float* __restrict__ rowsq, float* __restrict__ colsq,
+                                         bool want_rowsq, bool want_colsq) {
+  __shared__ float red[4][kMaxL];
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int nl = lane % 32, g = lane / 32;
+  const int l = L.l;
+  float csum[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) csum[v] = 0.f;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int64_t row = row0 + 32 * t + nl;
+    const bool in_i = row >= start && row < start + len;
+    const bool live = row < L.n;
+    float rs = 0.f;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int m = 8 * (v / 4) + 4 * g + (v % 4);
+      if (live && m < l) {
+        float r = in_i ? 0.f : (float)(R[row * l + m] - acc[t][v]);
+        R[row * l + m] = r;
+        rs = fmaf(r, r, rs);
+        csum[v] = fmaf(r, r, csum[v]);
+      }
+    }
+    if (want_rowsq) {
+      rs += __shfl_xor(rs, 32);
+      if (g == 0 && row < L.n_pad) rowsq[row] = live ? rs : 0.f;
+    }
+  }
+  if (want_colsq) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      float x = csum[v];
+      x += __shfl_xor(x, 1);
+      x += __shfl_xor(x, 2);
+      x += __shfl_xor(x, 4);
+      x += __shfl_xor(x, 8);
+      x += __shfl_xor(x, 16);
+      csum[v] = x;
+    }
+    if (nl == 0) {
+#pragma unroll
+      for (int v = 0; v < 16; ++v) red[wave][8 * (v / 4) + 4 * g + (v % 4)] = csum[v];
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxL) {
+      const int m = threadIdx.x;
+      float s = ((red[0][m] + red[1][m]) + red[2][m]) + red[3][m];
+      colsq[blockIdx.x * kMaxL + m] = m < l ? s : 0.f;
+    }
+  }
+}
+
+// BF16 tiles: KS K-steps of 16 prepared feature slots (3d + 6 <= 16 KS).
+template <int KERN, int KS>
+__global__ __launch_bounds__(256) void k_fused_bf16(Layout L, const uint16_t* __restrict__ xrow,
+                                                    const uint16_t* __restrict__ xcol,
+                                                    const uint16_t* __restrict__ dtile,
+                                                    const Ctl* __restrict__ ctl, int block,
+                                                    float* __restrict__ R,
+                                                    float* __restrict__ rowsq,
+                                                    float* __restrict__ colsq, int want_rowsq,
+                                                    int want_colsq) {
+  const int blk = block >= 0 ? block : ctl->sel;
+  const int64_t start = (int64_t)blk * L.b;
+  const int len = (int)std::min<int64_t>(L.b, L.n - start);
+  const int nch = (len + kChunk - 1) / kChunk;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int nl = lane % 32, g = lane / 32;
+  const int64_t row0 = (int64_t)blockIdx.x * kRowsWG + wave * 64;
+  constexpr int KF = 16 * KS;
+
+  bf16x8 brow[2][KS];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+      brow[t][ks] = load_bf16x8(xrow + (row0 + 32 * t + nl) * KF + 16 * ks + 8 * g);
+
+  f32x16 acc[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[t][v] = 0.f;
+
+  for (int ch = 0; ch < nch; ++ch) {
+    const int64_t cb = start + (int64_t)ch * kChunk;
+    bf16x8 acol[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) acol[ks] = load_bf16x8(xcol + (cb + nl) * KF + 16 * ks + 8 * g);
+    const bf16x8 d0 = load_bf16x8(dtile + (((size_t)ch * 2 + 0) * 64 + lane) * 8);
+    const bf16x8 d1 = load_bf16x8(dtile + (((size_t)ch * 2 + 1) * 64 + lane) * 8);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      f32x16 s;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) s[v] = 0.f;
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks)
+        s = __builtin_amdgcn_mfma_f32_32x32x16_bf16(acol[ks], brow[t][ks], s, 0, 0, 0);
+#pragma unroll
+      for (int v = 0; v < 16; ++v) s[v] = kmap_neg<KERN>(s[v]);
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(d0, pack8(s, 0), acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(d1, pack8(s, 8), acc[t], 0, 0, 0);
+    }
+  }
+  epilogue(L, row0, start, len, acc, R, rowsq, colsq, want_rowsq, want_colsq);
+}
+
+// FP32 tiles: exact differencing of the prepared (hi, lo) FP32 features, FP32
+// map, and the product on v_mfma_f32_32x32x2f32 (one kernel value per lane per
+// step).
+template <int KERN, int DP>
+__global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const float* __restrict__ xs,
+                                                    const float* __restrict__ dtile,
+                                                    const Ctl* __restrict__ ctl, int block,
+                                                    float* __restrict__ R,
+                                                    float* __restrict__ rowsq,
+                                                    float* __restrict__ colsq, int want_rowsq,
+                                                    int want_colsq) {
+  const int blk = block >= 0 ? block : ctl->sel;
+  const int64_t start = (int64_t)blk * L.b;
+  const int len = (int)std::min<int64_t>(L.b, L.n - start);
+  const int nch = (len + kChunk - 1) / kChunk;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int nl = lane % 32, g = lane / 32;
+  const int64_t row0 = (int64_t)blockIdx.x * kRowsWG + wave * 64;
+
+  // row features as (hi, lo) FP32 pairs
+  float xr[2][2 * DP];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int k = 0; k < 2 * DP; k += 4) {
+      float4 v = *reinterpret_cast<const float4*>(xs + (row0 + 32 * t + nl) * 2 * DP + k);
+      xr[t][k] = v.x;
+      xr[t][k + 1] = v.y;
+      xr[t][k + 2] = v.z;
+      xr[t][k + 3] = v.w;
+    }
+  // Each chunk's 32 products accumulate in FP32 on the matrix cores; the chunk
+  // sums then accumulate in FP64, so the rounding of the long sum over the
+  // block stays at the level of one chunk.
+  f64x16 acc[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[t][v] = 0.0;
+
+  for (int ch = 0; ch < nch; ++ch) {
+    const int64_t cb = start + (int64_t)ch * kChunk;
+    f32x16 part[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) part[t][v] = 0.f;
+#pragma unroll 2
+    for (int st = 0; st < 16; ++st) {
+      const int cc = 2 * st + g;  // this lane's chunk column
+      float xc[2 * DP];
+#pragma unroll
+      for (int k = 0; k < 2 * DP; k += 4) {
+        float4 v = *reinterpret_cast<const float4*>(xs + (cb + cc) * 2 * DP + k);
+        xc[k] = v.x;
+        xc[k + 1] = v.y;
+        xc[k + 2] = v.z;
+        xc[k + 3] = v.w;
+      }
+      const float dv = dtile[((int64_t)ch * kChunk + cc) * kMaxL + nl];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        float r2 = 0.f;
+#pragma unroll
+        for (int k = 0; k < DP; ++k) {
+          float df = (xr[t][k] - xc[k]) + (xr[t][DP + k] - xc[DP + k]);
+          r2 = fmaf(df, df, r2);
+        }
+        const float kv = kmap_neg<KERN>(-r2);
+        part[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(dv, kv, part[t], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[t][v] += (double)part[t][v];
+  }
+  epilogue(L, row0, start, len, acc, R, rowsq, colsq, want_rowsq, want_colsq);
+}
+
+template <int KERN>
+hipError_t launch_bf16(const Layout& L, const Dev& D, int32_t block, float* R, bool wr, bool wc,
+                       hipStream_t st) {
+  const dim3 g(L.nwg), t(256);
+  const uint16_t* dt = (const uint16_t*)D.dtile;
+  switch (L.ks) {
+    case 1: hipLaunchKernelGGL((k_fused_bf16<KERN, 1>), g, t, 0, st, L, D.xrow, D.xcol, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 2: hipLaunchKernelGGL((k_fused_bf16<KERN, 2>), g, t, 0, st, L, D.xrow, D.xcol, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 3: hipLaunchKernelGGL((k_fused_bf16<KERN, 3>), g, t, 0, st, L, D.xrow, D.xcol, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 4: hipLaunchKernelGGL((k_fused_bf16<KERN, 4>), g, t, 0, st, L, D.xrow, D.xcol, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int KERN>
+hipError_t launch_fp32(const Layout& L, const Dev& D, int32_t block, float* R, bool wr, bool wc,
+                       hipStream_t st) {
+  const dim3 g(L.nwg), t(256);
+  const float* dt = (const float*)D.dtile;
+  switch (L.dp) {
+    case 4: hipLaunchKernelGGL((k_fused_fp32<KERN, 4>), g, t, 0, st, L, D.xs, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 8: hipLaunchKernelGGL((k_fused_fp32<KERN, 8>), g, t, 0, st, L, D.xs, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 12: hipLaunchKernelGGL((k_fused_fp32<KERN, 12>), g, t, 0, st, L, D.xs, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 16: hipLaunchKernelGGL((k_fused_fp32<KERN, 16>), g, t, 0, st, L, D.xs, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 20: hipLaunchKernelGGL((k_fused_fp32<KERN, 20>), g, t, 0, st, L, D.xs, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fused_update(const Layout& L, const Dev& D, int32_t block, float* R,
+                               bool want_rowsq, bool want_colsq, hipStream_t st) {
+  if (L.tile == 1) {
+    switch (L.kernel) {
+      case 0: return launch_bf16<0>(L, D, block, R, want_rowsq, want_colsq, st);
+      case 1: return launch_bf16<1>(L, D, block, R, want_rowsq, want_colsq, st);
+      default: return launch_bf16<2>(L, D, block, R, want_rowsq, want_colsq, st);
+    }
+  }
+  switch (L.kernel) {
+    case 0: return launch_fp32<0>(L, D, block, R, want_rowsq, want_colsq, st);
+    case 1: return launch_fp32<1>(L, D, block, R, want_rowsq, want_colsq, st);
+    default: return launch_fp32<2>(L, D, block, R, want_rowsq, want_colsq, st);
+  }
+}
+
+}  // namespace ap

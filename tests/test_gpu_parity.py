@@ -1,0 +1,285 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Every case draws its inputs from the seeded generators; the oracle and the GPU
+see the same FP32 values (the oracle widened to FP64). Tolerances:
+  - cached block inverses (FP64): 1e-9 relative to the largest entry, times the
+    block's condition number over 1e4;
+  - FP32 tiles: iterates W within 1e-5 relative (Frobenius) of the oracle's.
+    The residual R is FP32, so after an update its error is bounded by FP32
+    rounding of K^_{:,I} delta: ||dR|| <= 1e-5 ||R|| + 2 u32 || |K^_{:,I}| |delta| ||
+    (u32 = 2^-24). Where that amplification factor || |K||delta| || / ||R|| is
+    large (ill-conditioned cases) the iterates inherit it, and the bar becomes
+    4 u32 times the factor; an FP32 emulation on the CPU shows the same size;
+  - BF16 tiles: one update within 2e-2 relative; solves reach a true FP64
+    relative residual below the tolerance;
+  - FP64 true residual: 1e-9 relative to ||B||.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import apo
+from paper_2310_17137_amd import gen
+from tests.helpers import dense_khat, to_oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2310_17137_amd import ap  # noqa: E402
+
+
+def _gpu(w, tile=ap.TILE_FP32, **over):
+    print(f"[case] {w.name} n={w.n} d={w.d} l={w.l} b={w.b} kernel={w.kernel} tile={tile} {over}",
+          flush=True)
+    return ap.from_workload(w, tile=tile, **over)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+CASES = [
+    # (seed, n, d, l, b, kernel, noise, ell)
+    (0, 1000, 3, 1, 100, apo.RBF, 0.1, 0.3),         # b not a multiple of 64, ragged last block
+    (1, 777, 5, 7, 128, apo.MATERN32, 0.05, 0.6),    # ragged n, odd l
+    (2, 1536, 8, 16, 512, apo.MATERN52, 0.01, 1.2),
+    (3, 700, 11, 32, 256, apo.RBF, 0.02, 0.9),       # full RHS bucket, d = 11
+    (4, 300, 16, 3, 300, apo.MATERN52, 0.1, 2.0),    # one block (b = n), d = 16
+    (5, 2048, 2, 32, 64, apo.MATERN32, 0.001, 0.2),  # many small blocks
+]
+
+
+def _small(case, order=apo.CYCLIC):
+    seed, n, d, l, b, kern, noise, ell = case
+    rng = np.random.default_rng(100 + seed)
+    ls = ell * rng.uniform(0.7, 1.4, size=d)
+    return gen.small(seed, n, d, l, b, kernel=kern, noise=noise, ell=ls, outputscale=1.3,
+                     order=order, dist="normal" if seed % 2 else "uniform")
+
+
+@pytest.mark.parametrize("case", CASES[:5])
+def test_block_inverses_match_dense(case):
+    w = _small(case)
+    s, B, W, R = _gpu(w)
+    p = to_oracle(w)
+    K = dense_khat(p)
+    for j in sorted({0, s.m // 2, s.m - 1}):
+        blk = p.block(j)
+        ref = np.linalg.inv(K[blk, blk])
+        got = s.block_inverse(j).cpu().numpy()
+        kappa = np.linalg.cond(K[blk, blk])
+        tol = 1e-9 * max(1.0, kappa / 1e4) * np.abs(ref).max()
+        np.testing.assert_allclose(got, ref, rtol=0, atol=tol)
+
+
+U32 = 2.0 ** -24
+
+
+def _amplification(p, K, blk, delta, R_new):
+    s = p.block(blk)
+    return np.linalg.norm(np.abs(K[:, s]) @ np.abs(delta)) / max(np.linalg.norm(R_new), 1e-300)
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_single_update_fp32(case):
+    w = _small(case)
+    s, B, W, R = _gpu(w)
+    s.reset(B, W, R)
+    p = to_oracle(w)
+    L = apo.factor(p)
+    K = dense_khat(p)
+    Wo, Ro = np.zeros_like(p.B), p.B.copy()
+    tol = 1e-5
+    for blk in [s.m - 1, 0]:
+        delta = apo.update(p, L, Wo, Ro, blk)
+        s.update(B, W, R, blk)
+        torch.cuda.synchronize()
+        # the first step is an FP64 solve of the same FP32 R_I; the second one
+        # sees the first update's FP32 rounding, amplified as for the iterates
+        assert _rel(W.cpu().numpy(), Wo) < tol
+        tol = max(1e-5, 4 * U32 * _amplification(p, K, blk, delta, Ro))
+        sl = p.block(blk)
+        bound = 1e-5 * np.linalg.norm(Ro) + 2 * U32 * np.linalg.norm(np.abs(K[:, sl]) @ np.abs(delta))
+        assert np.linalg.norm(R.cpu().numpy() - Ro) <= bound
+        assert np.all(R.cpu().numpy()[sl] == 0.0)  # the projection zeroes R_I
+
+
+def _epoch_tol(p, L, K):
+    Wt, Rt = np.zeros_like(p.B), p.B.copy()
+    delta = apo.update(p, L, Wt, Rt, 0)
+    return max(1e-5, 4 * U32 * _amplification(p, K, 0, delta, Rt))
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_epochs_fp32_match_oracle(case):
+    w = _small(case)
+    s, B, W, R = _gpu(w)
+    s.reset(B, W, R)
+    p = to_oracle(w)
+    L = apo.factor(p)
+    K = dense_khat(p)
+    tol = _epoch_tol(p, L, K) if p.m > 1 else 1e-5
+    print(f"[tol] W iterates within {tol:.2e}", flush=True)
+    Wo, Ro = np.zeros_like(p.B), p.B.copy()
+    for ep in range(3):
+        s.epoch(B, W, R, 1)
+        apo.epoch(p, L, Wo, Ro)
+        rho, cols = s.rel_residual()
+        assert _rel(W.cpu().numpy(), Wo) < tol, ep
+        rho_o = apo.rel_residual(p, Ro)
+        assert abs(rho - rho_o) <= max(tol * rho_o, 1e-7)
+
+
+@pytest.mark.parametrize("case", [CASES[1], CASES[3], CASES[5]])
+def test_greedy_fp32_match_oracle(case):
+    w = _small(case, order=apo.GREEDY)
+    s, B, W, R = _gpu(w)
+    s.reset(B, W, R)
+    p = to_oracle(w)
+    L = apo.factor(p)
+    Wo, Ro = np.zeros_like(p.B), p.B.copy()
+    for _ in range(2):
+        s.epoch(B, W, R, 1)
+        apo.epoch(p, L, Wo, Ro)
+        torch.cuda.synchronize()
+        assert _rel(W.cpu().numpy(), Wo) < 1e-5
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_single_update_bf16(case):
+    w = _small(case)
+    s, B, W, R = _gpu(w, tile=ap.TILE_BF16)
+    s.reset(B, W, R)
+    p = to_oracle(w)
+    L = apo.factor(p)
+    Wo, Ro = np.zeros_like(p.B), p.B.copy()
+    blk = s.m // 2
+    s.update(B, W, R, blk)
+    delta = apo.update(p, L, Wo, Ro, blk)
+    torch.cuda.synchronize()
+    # the first update's W is an FP64 solve of the same R_I: as tight as FP32
+    assert _rel(W.cpu().numpy(), Wo) < 1e-5
+    # R - K^[:, I] delta with BF16 tiles (8-bit significands for the kernel
+    # values and the step): the error of the change is bounded by 2^-7 times
+    # the magnitude of the products, || |K^[:, I]| |delta| ||.
+    K = dense_khat(p)
+    sl = p.block(blk)
+    mag = np.linalg.norm(np.abs(K[:, sl]) @ np.abs(delta))
+    dR = R.cpu().numpy() - p.B
+    dRo = Ro - p.B
+    err = np.linalg.norm(dR - dRo)
+    print(f"[bf16] |d(dR)| / |dR| = {err / np.linalg.norm(dRo):.3e}, bound {2**-7 * mag / np.linalg.norm(dRo):.3e}")
+    assert err <= 2.0 ** -7 * mag
+    assert np.all(R.cpu().numpy()[sl] == 0.0)
+
+
+@pytest.mark.parametrize("case", CASES[:4])
+def test_true_residual_fp64(case):
+    w = _small(case)
+    s, B, W, R = _gpu(w)
+    s.reset(B, W, R)
+    s.epoch(B, W, R, 2)
+    Rt = torch.empty_like(R)
+    cols = s.residual(B, W, R, R_out=Rt)
+    p = to_oracle(w)
+    Wg = W.cpu().numpy()
+    ref = p.B - dense_khat(p) @ Wg
+    nb = np.linalg.norm(p.B)
+    assert np.linalg.norm(Rt.cpu().numpy() - ref) <= 1e-6 * nb  # stored as FP32
+    ref_cols = np.linalg.norm(ref, axis=0) / np.linalg.norm(p.B, axis=0)
+    np.testing.assert_allclose(cols, ref_cols, rtol=1e-9)
+    # the maintained FP32 residual drifts from the true one by FP32 rounding
+    tol = _epoch_tol(p, apo.factor(p), dense_khat(p))
+    assert np.linalg.norm(R.cpu().numpy() - ref) <= tol * nb
+
+
+def test_c1_trajectory_fp32():
+    """C1 (n = 4096, RBF, b = 512, one RHS): 30 epochs, iterates within 1e-5."""
+    w = gen.c1()
+    s, B, W, R = _gpu(w)
+    s.reset(B, W, R)
+    p = to_oracle(w)
+    L = apo.factor(p)
+    Wo, Ro = np.zeros_like(p.B), p.B.copy()
+    worst = 0.0
+    for ep in range(30):
+        s.epoch(B, W, R, 1)
+        apo.epoch(p, L, Wo, Ro)
+        rho, _ = s.rel_residual()
+        e = _rel(W.cpu().numpy(), Wo)
+        rho_o = apo.rel_residual(p, Ro)
+        print(f"[c1] epoch {ep + 1} rho {rho:.8f} oracle {rho_o:.8f} W err {e:.3e}", flush=True)
+        worst = max(worst, e)
+        assert rho == pytest.approx(rho_o, rel=1e-4)  # a norm of the FP32 residual
+    assert worst < 1e-5
+
+
+def test_solve_mixed_reaches_tolerance():
+    """BF16 tiles with FP64 refinement reach a true relative residual < 1e-2."""
+    w = gen.small(7, 3000, 3, 8, 256, kernel=apo.RBF, noise=0.1, ell=0.05)
+    w.tol, w.refine_every, w.max_epochs = 1e-2, 5, 200
+    s, B, W, R = _gpu(w, tile=ap.TILE_BF16)
+    st = s.solve(B, W, R)
+    assert st.converged, st
+    assert st.rho_true < 1e-2
+    p = to_oracle(w)
+    rows = np.arange(0, w.n, 37)
+    true = apo.residual_rows(p, W.cpu().numpy(), rows)
+    col = np.linalg.norm(true, axis=0) / np.linalg.norm(p.B[rows], axis=0)
+    assert col.mean() < 3e-2  # row-sampled estimate of the same ratio
+
+
+def test_solve_fp32_matches_oracle_solve():
+    w = gen.small(8, 2000, 3, 4, 200, kernel=apo.MATERN52, noise=0.1, ell=0.04)
+    w.tol, w.max_epochs, w.min_epochs = 1e-3, 300, 2
+    s, B, W, R = _gpu(w)
+    st = s.solve(B, W, R)
+    p = to_oracle(w)
+    res = apo.solve(p)
+    assert st.converged == res.converged
+    assert st.epochs == res.epochs
+    assert _rel(W.cpu().numpy(), res.W) < 1e-5
+
+
+def test_not_positive_definite_reports_block():
+    w = gen.small(9, 600, 2, 1, 100)
+    X = w.X.copy()
+    X[333] = X[310]  # duplicate inside block 3 (rows 300..399)
+    Xt = torch.from_numpy(X).cuda()
+    # a short lengthscale keeps every other block far from singular
+    with pytest.raises(ap.ApError) as e:
+        ap.Solver(Xt, l=1, b=100, kernel=ap.RBF, lengthscale=0.005, noise=0.0)
+    assert e.value.code == ap.ERR_NOT_PD
+    assert "block 3" in str(e.value)
+    # by-index noise: the same points are fine
+    ap.Solver(Xt, l=1, b=100, kernel=ap.RBF, lengthscale=0.005, noise=1e-3)
+
+
+def test_invalid_arguments_and_workspace():
+    X = torch.rand(100, 3, device="cuda")
+    with pytest.raises(ap.ApError) as e:
+        ap.Solver(X, l=1, b=0, kernel=ap.RBF, lengthscale=0.5)
+    assert e.value.code == ap.ERR_INVALID_ARG
+    small = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ap.ApError) as e:
+        ap.Solver(X, l=1, b=50, kernel=ap.RBF, lengthscale=0.5, workspace=small)
+    assert e.value.code == ap.ERR_WORKSPACE
+    s = ap.Solver(X, l=1, b=50, kernel=ap.RBF, lengthscale=0.5)
+    B = torch.rand(100, 1, device="cuda")
+    W, R = s.new_state(B)
+    with pytest.raises(ap.ApError):
+        s.update(B, W, R, 2)  # block index out of range (m = 2)
+
+
+def test_nonfinite_rhs_is_reported():
+    X = torch.rand(200, 3, device="cuda")
+    s = ap.Solver(X, l=2, b=50, kernel=ap.RBF, lengthscale=0.5)
+    B = torch.rand(200, 2, device="cuda")
+    B[17, 1] = float("nan")
+    W, R = s.new_state(B)
+    s.reset(B, W, R)
+    s.epoch(B, W, R, 1)
+    with pytest.raises(ap.ApError) as e:
+        s.rel_residual()
+    assert e.value.code == ap.ERR_NONFINITE

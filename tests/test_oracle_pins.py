@@ -357,3 +357,16 @@ def test_c1_trajectory_monotone_and_consistent():
     rows = np.arange(0, 4096, 64)
     true = apo.residual_rows(p, res.W, rows)
     np.testing.assert_allclose(true, res.R[rows], rtol=0, atol=1e-10)
+
+
+def test_single_block_factor_and_update_agree_with_batched():
+    p = _problem(n=300, b=128, kernel=apo.MATERN32)
+    L = apo.factor(p)
+    for j in range(p.m):
+        np.testing.assert_array_equal(apo.factor_one(p, j), apo.block_factor(L, p, j))
+    W1, R1 = np.zeros_like(p.B), p.B.copy()
+    W2, R2 = np.zeros_like(p.B), p.B.copy()
+    apo.update(p, L, W1, R1, 2)
+    apo.update_block(p, apo.factor_one(p, 2), W2, R2, 2)
+    np.testing.assert_array_equal(W1, W2)
+    np.testing.assert_array_equal(R1, R2)
