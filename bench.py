@@ -37,7 +37,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_TRANS_PER_S = 256 * 32 * 2.4e9
 
 
-TILE_NAMES = {0: "fp32", 1: "bf16"}
+TILE_NAMES = {0: "fp32", 1: "bf16", 2: "split"}
 
 
 def log(*a):
@@ -97,6 +97,7 @@ def main():
     ap_.add_argument("--warmup", type=int, default=1)
     ap_.add_argument("--workload", default="c3")
     ap_.add_argument("--bf16-steps", type=int, default=1)
+    ap_.add_argument("--fp32-steps", type=int, default=1)
     ap_.add_argument("--no-bf16", action="store_true")
     ap_.add_argument("--cpu-updates", type=int, default=2)
     ap_.add_argument("--no-cpu", action="store_true")
@@ -191,8 +192,10 @@ def main():
         return res
 
     paths = {}
-    main_tile = ap.TILE_FP32
-    paths["fp32"] = run_path(ap.TILE_FP32, args.steps, args.warmup, not args.no_true_residual)
+    main_tile = ap.TILE_SPLIT
+    paths["split"] = run_path(ap.TILE_SPLIT, args.steps, args.warmup, not args.no_true_residual)
+    if args.fp32_steps > 0:
+        paths["fp32"] = run_path(ap.TILE_FP32, args.fp32_steps, 0, False)
     if not args.no_bf16:
         paths["bf16"] = run_path(ap.TILE_BF16, args.bf16_steps, 1, False)
     main = paths[TILE_NAMES[main_tile]]
@@ -203,6 +206,8 @@ def main():
     flops_launch = 2.0 * (w.d + w.l) * entries_per_launch
     achieved = flops_launch / avg / 1e12
     peak = PEAK_FP32_TFLOPS if main_tile == ap.TILE_FP32 else PEAK_BF16_TFLOPS
+    # the split path runs six BF16 partial products per tile entry and column
+    mfma_flops_launch = flops_launch * (6 if main_tile == ap.TILE_SPLIT else 1)
     trans_rate = trans_per_entry(w.kernel) * entries_per_launch / avg
     bytes_launch = 2.0 * w.n * w.l * 4 + w.n * w.d * 8
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak,
@@ -211,6 +216,7 @@ def main():
                 "avg_launch_us": avg * 1e6,
                 "flops_per_entry": 2 * (w.d + w.l), "entries_per_launch": entries_per_launch,
                 "transcendental_frac": trans_rate / PEAK_TRANS_PER_S,
+                "issued_mfma_tflops": mfma_flops_launch / avg / 1e12,
                 "hbm_gbs": bytes_launch / avg / 1e9}
 
     cpu = None

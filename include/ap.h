@@ -68,13 +68,18 @@ typedef enum { AP_CYCLIC = 0, AP_GREEDY = 1 } ap_order;
 
 /* Arithmetic of the fused residual update (the kernel tiles K^_{:,I} and their
  * product with the block step). Block factors, block solves, W and the true
- * residual are FP64 in both; R is FP32 in both.
- *  AP_TILE_FP32: r^2 by exact differencing in FP32, kernel map in FP32, product
- *                with the step on FP32 matrix cores.
- *  AP_TILE_BF16: x.x' on BF16 matrix cores with a two-term (hi + lo) split of
- *                every feature, kernel map in FP32, tile and step rounded to
- *                BF16 for the product, FP32 accumulation. */
-typedef enum { AP_TILE_FP32 = 0, AP_TILE_BF16 = 1 } ap_tile;
+ * residual are FP64 in all; R is FP32 in all.
+ *  AP_TILE_FP32:  r^2 by exact differencing of (hi, lo) FP32 features, kernel
+ *                 map in FP32, product with the step on FP32 matrix cores.
+ *  AP_TILE_BF16:  x.x' on BF16 matrix cores with a two-term (hi + lo) split of
+ *                 every feature, kernel map in FP32, tile and step rounded to
+ *                 BF16 for the product, FP32 accumulation. About 8 significant
+ *                 bits per product: for well-conditioned systems only.
+ *  AP_TILE_SPLIT: r^2 by exact differencing in FP32, kernel map in FP32, tile
+ *                 and step each split into three BF16 terms and multiplied on
+ *                 BF16 matrix cores (six partial products), FP32 accumulation
+ *                 per 32 columns and FP64 across them: FP32-grade products. */
+typedef enum { AP_TILE_FP32 = 0, AP_TILE_BF16 = 1, AP_TILE_SPLIT = 2 } ap_tile;
 
 /* Limits of this build: 1 <= d <= 20, 1 <= l <= 32, 1 <= b <= 4096, b <= n,
  * n < 2^31. Larger sizes return AP_ERR_UNSUPPORTED. */

@@ -18,8 +18,6 @@ constexpr int kMaxL = 32;
 constexpr int kT = 64;
 // K-split of the FP64 block solve.
 constexpr int kBsSplit = 16;
-// Rows per workgroup of the FP64 true residual.
-constexpr int kResRows = 64;
 constexpr int kMaxD = 20;
 
 // Device control block at the start of the workspace.

@@ -29,7 +29,7 @@ bool make_layout(int64_t n, int32_t d, int32_t l, int32_t b, int32_t kernel, int
   o.dp = (d + 3) / 4 * 4;
   o.n_pad = (n + 32 + kRowsWG - 1) / kRowsWG * kRowsWG;
   o.nwg = (int32_t)(o.n_pad / kRowsWG);
-  o.nwg_res = (int32_t)((n + kResRows - 1) / kResRows);
+  o.nwg_res = (int32_t)((n + 127) / 128);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t at = off;
@@ -37,7 +37,9 @@ bool make_layout(int64_t n, int32_t d, int32_t l, int32_t b, int32_t kernel, int
     return at;
   };
   o.off_ctl = take(sizeof(Ctl));
-  o.off_xs = take(tile == 0 ? (size_t)o.n_pad * 2 * o.dp * sizeof(float) : 0);
+  o.off_xs = take(tile == 0   ? (size_t)o.n_pad * 2 * o.dp * sizeof(float)
+                  : tile == 2 ? (size_t)o.n_pad * o.dp * sizeof(float)
+                              : 0);
   o.off_xrow = take(tile == 1 ? (size_t)o.n_pad * 16 * o.ks * 2 : 0);
   o.off_xcol = take(tile == 1 ? (size_t)o.n_pad * 16 * o.ks * 2 : 0);
   o.off_kinv = take((size_t)o.m * o.b_pad * o.b_pad * sizeof(double));
@@ -45,7 +47,7 @@ bool make_layout(int64_t n, int32_t d, int32_t l, int32_t b, int32_t kernel, int
   o.off_panel = take((size_t)o.m * o.b_pad * kT * sizeof(double));
   o.off_delta = take((size_t)o.b_pad * kMaxL * sizeof(double));
   o.off_bspart = take((size_t)kBsSplit * o.b_pad * kMaxL * sizeof(double));
-  o.off_dtile = take((size_t)o.b_pad * kMaxL * sizeof(float));
+  o.off_dtile = take((size_t)o.b_pad * 2 * kMaxL * sizeof(float));
   o.off_rowsq = take((size_t)o.n_pad * sizeof(float));
   o.off_colsq = take((size_t)o.nwg * kMaxL * sizeof(float));
   o.off_blocknorm = take((size_t)o.m * sizeof(double));
@@ -131,7 +133,8 @@ __global__ void k_mu_final(Layout L, const double* __restrict__ part, Ctl* ctl) 
 
 // Prepared copies of the features, v = (x - mu) / ell * c (one thread per row).
 // FP32 path: xs[i] = [vh, vl], two FP32 terms with v = vh + vl to 2^-48, so a
-// difference of two points is formed without the rounding of v itself. BF16 path: v = vh + vl (two BF16 terms), |v|^2 = nh + nm + nl
+// difference of two points is formed without the rounding of v itself. Split
+// path: xs[i] = v in FP32. BF16 path: v = vh + vl (two BF16 terms), |v|^2 = nh + nm + nl
 // (three BF16 terms), and the row / column operands
 //   row: [vh, vh, vl, -nh, -nm, -nl, 1, 1, 1, 0...]
 //   col: [2vh, 2vl, 2vh, 1, 1, 1, -nh, -nm, -nl, 0...]
@@ -155,6 +158,14 @@ __global__ __launch_bounds__(256) void k_prep(Layout L, Params P, const float* _
       }
       xs[i * 2 * L.dp + k] = vh;
       xs[i * 2 * L.dp + L.dp + k] = vl;
+    }
+    return;
+  }
+  if (L.tile == 2) {
+    for (int k = 0; k < L.dp; ++k) {
+      float v = 0.f;
+      if (i < L.n && k < d) v = (float)(((double)X[i * d + k] - ctl->mu[k]) / P.ell[k] * c);
+      xs[i * L.dp + k] = v;
     }
     return;
   }

@@ -2,8 +2,8 @@
 // residual_equality: the maintained residual equals this in exact arithmetic,
 // so recomputing it removes the drift of the reduced-precision update).
 // Exact differencing of the FP32 inputs widened to FP64, FP64 kernel map, FP64
-// accumulation in a fixed column order. One lane per row; the columns' features
-// and weights are staged through LDS and read by all lanes at once.
+// accumulation in a fixed column order on the FP64 matrix cores. The columns'
+// features and weights are staged through LDS.
 #include <algorithm>
 
 #include "ap_internal.h"
@@ -11,87 +11,136 @@
 namespace ap {
 namespace {
 
-constexpr int kCols = 64;  // columns staged per step
+constexpr int kCols = 64;  // columns staged in LDS per step
+constexpr int kResWG = 128; // rows per workgroup: 4 waves x two 16-row tiles
 
-template <int KERN, int LB>
-__global__ __launch_bounds__(kResRows) void k_residual(Layout L, Params P,
-                                                       const float* __restrict__ X,
-                                                       const float* __restrict__ B,
-                                                       const double* __restrict__ W,
-                                                       float* __restrict__ Rout,
-                                                       float* __restrict__ rowsq,
-                                                       double* __restrict__ part) {
-  __shared__ double sx[kCols][kMaxD];
-  __shared__ double sw[kCols][LB];
-  __shared__ double sq[LB][kResRows];
-  const int d = L.d, l = L.l;
-  const int64_t i = (int64_t)blockIdx.x * kResRows + threadIdx.x;
-  const bool live = i < L.n;
-  double inv_ell[kMaxD], xi[kMaxD];
-#pragma unroll
-  for (int k = 0; k < kMaxD; ++k) {
-    inv_ell[k] = k < d ? 1.0 / P.ell[k] : 0.0;
-    xi[k] = (live && k < d) ? (double)X[i * d + k] : 0.0;
+typedef __attribute__((ext_vector_type(4))) double f64x4;
+
+template <int KERN>
+__device__ __forceinline__ double kernel_fp64(double r2, const Params& P) {
+  if constexpr (KERN == 0) {
+    return P.s * exp(-0.5 * r2);
+  } else if constexpr (KERN == 1) {
+    double t = 1.7320508075688772 * sqrt(r2);
+    return P.s * (1.0 + t) * exp(-t);
+  } else {
+    double r = sqrt(r2), t = 2.23606797749979 * r;
+    return P.s * (1.0 + t + (5.0 / 3.0) * r2) * exp(-t);
   }
-  double acc[LB];
+}
+
+// The product sum_j K^_ij W_jc runs on v_mfma_f64_16x16x4f64: per step of 4
+// columns a lane evaluates one kernel entry per row tile (row lane % 16, column
+// lane / 16) in FP64 on the vector ALUs, and the matrix cores accumulate
+// acc[c][i] += W^T[c][j] K^T[j][i] for 16 right-hand sides per half (NH halves).
+template <int KERN, int DP, int NH>
+__global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const float* __restrict__ X,
+                                                  const float* __restrict__ B,
+                                                  const double* __restrict__ W,
+                                                  float* __restrict__ Rout,
+                                                  float* __restrict__ rowsq,
+                                                  double* __restrict__ part) {
+  __shared__ double sx[kCols][DP];
+  __shared__ double sw[kCols][16 * NH];
+  __shared__ double red[4][16 * NH];
+  const int d = L.d, l = L.l;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int ln = lane % 16, lg = lane / 16;
+  const int64_t row0 = (int64_t)blockIdx.x * kResWG + wave * 32;
+  double inv_ell[DP], xi[2][DP];
 #pragma unroll
-  for (int c = 0; c < LB; ++c) acc[c] = 0.0;
+  for (int k = 0; k < DP; ++k) inv_ell[k] = k < d ? 1.0 / P.ell[k] : 0.0;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int64_t i = row0 + 16 * t + ln;
+#pragma unroll
+    for (int k = 0; k < DP; ++k) xi[t][k] = (i < L.n && k < d) ? (double)X[i * d + k] : 0.0;
+  }
+  f64x4 acc[2][NH];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int h = 0; h < NH; ++h) acc[t][h] = f64x4{0.0, 0.0, 0.0, 0.0};
+
   for (int64_t j0 = 0; j0 < L.n; j0 += kCols) {
-    const int cols = (int)std::min<int64_t>(kCols, L.n - j0);
     __syncthreads();
-    for (int e = threadIdx.x; e < kCols * kMaxD; e += kResRows) {
-      int jj = e / kMaxD, k = e % kMaxD;
-      sx[jj][k] = (jj < cols && k < d) ? (double)X[(j0 + jj) * d + k] : 0.0;
+    for (int e = threadIdx.x; e < kCols * DP; e += 256) {
+      const int jj = e / DP, k = e % DP;
+      sx[jj][k] = (j0 + jj < L.n && k < d) ? (double)X[(j0 + jj) * d + k] : 0.0;
     }
-    for (int e = threadIdx.x; e < kCols * LB; e += kResRows) {
-      int jj = e / LB, c = e % LB;
-      sw[jj][c] = (jj < cols && c < l) ? W[(j0 + jj) * l + c] : 0.0;
+    for (int e = threadIdx.x; e < kCols * 16 * NH; e += 256) {
+      const int jj = e / (16 * NH), c = e % (16 * NH);
+      sw[jj][c] = (j0 + jj < L.n && c < l) ? W[(j0 + jj) * l + c] : 0.0;
     }
     __syncthreads();
-    for (int jj = 0; jj < cols; ++jj) {
-      double r2 = 0.0;
+    for (int st = 0; st < kCols / 4; ++st) {
+      const int jj = 4 * st + lg;
+      const int64_t j = j0 + jj;
+      double a[NH];
 #pragma unroll
-      for (int k = 0; k < kMaxD; ++k) {
-        if (k < d) {
-          double t = (xi[k] - sx[jj][k]) * inv_ell[k];
-          r2 = fma(t, t, r2);
+      for (int h = 0; h < NH; ++h) a[h] = sw[jj][16 * h + ln];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        double r2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < DP; ++k) {
+          const double df = (xi[t][k] - sx[jj][k]) * inv_ell[k];
+          r2 = fma(df, df, r2);
+        }
+        double kv = kernel_fp64<KERN>(r2, P);
+        if (j == row0 + 16 * t + ln) kv += P.noise;
+#pragma unroll
+        for (int h = 0; h < NH; ++h)
+          acc[t][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h], kv, acc[t][h], 0, 0, 0);
+      }
+    }
+  }
+  // lane holds acc[t][h][q] for row row0 + 16 t + lane % 16 and right-hand side
+  // c = 16 h + lane / 16 + 4 q (the FP64 16x16 accumulator layout)
+  double csum[NH][4];
+#pragma unroll
+  for (int h = 0; h < NH; ++h)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) csum[h][q] = 0.0;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int64_t i = row0 + 16 * t + ln;
+    const bool live = i < L.n;
+    double rs = 0.0;
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = 16 * h + lg + 4 * q;
+        if (live && c < l) {
+          const double r = (double)B[i * l + c] - acc[t][h][q];
+          Rout[i * l + c] = (float)r;
+          rs = fma(r, r, rs);
+          csum[h][q] = fma(r, r, csum[h][q]);
         }
       }
-      double kv;
-      if constexpr (KERN == 0) {
-        kv = P.s * exp(-0.5 * r2);
-      } else if constexpr (KERN == 1) {
-        double t = 1.7320508075688772 * sqrt(r2);
-        kv = P.s * (1.0 + t) * exp(-t);
-      } else {
-        double r = sqrt(r2), t = 2.23606797749979 * r;
-        kv = P.s * (1.0 + t + (5.0 / 3.0) * r2) * exp(-t);
-      }
-      if (j0 + jj == i) kv += P.noise;
-#pragma unroll
-      for (int c = 0; c < LB; ++c) acc[c] = fma(kv, sw[jj][c], acc[c]);
-    }
+    rs += __shfl_xor(rs, 16);
+    rs += __shfl_xor(rs, 32);
+    if (rowsq && live && lg == 0) rowsq[i] = (float)rs;
   }
-  double rs = 0.0;
 #pragma unroll
-  for (int c = 0; c < LB; ++c) {
-    double r = 0.0;
-    if (live && c < l) {
-      r = (double)B[i * l + c] - acc[c];
-      Rout[i * l + c] = (float)r;
-      rs = fma(r, r, rs);
+  for (int h = 0; h < NH; ++h)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double x = csum[h][q];
+      x += __shfl_xor(x, 1);
+      x += __shfl_xor(x, 2);
+      x += __shfl_xor(x, 4);
+      x += __shfl_xor(x, 8);
+      if (ln == 0) red[wave][16 * h + lg + 4 * q] = x;
     }
-    sq[c][threadIdx.x] = r * r;
-  }
-  if (rowsq && live) rowsq[i] = (float)rs;
   __syncthreads();
-  for (int s = kResRows / 2; s > 0; s >>= 1) {
-    for (int c = 0; c < LB; ++c)
-      if (threadIdx.x < s) sq[c][threadIdx.x] += sq[c][threadIdx.x + s];
-    __syncthreads();
+  if (threadIdx.x < kMaxL) {
+    const int c = threadIdx.x;
+    double v = 0.0;
+    if (c < 16 * NH) v = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+    part[(size_t)blockIdx.x * kMaxL + c] = c < l ? v : 0.0;
   }
-  if (threadIdx.x < kMaxL)
-    part[(size_t)blockIdx.x * kMaxL + threadIdx.x] = threadIdx.x < LB ? sq[threadIdx.x][0] : 0.0;
 }
 
 __global__ __launch_bounds__(256) void k_residual_final(Layout L, const double* __restrict__ part,
@@ -124,20 +173,26 @@ __global__ __launch_bounds__(256) void k_residual_final(Layout L, const double* 
   }
 }
 
+template <int KERN, int NH>
+void launch_res_d(const Layout& L, const Dev& D, const Params& P, const float* X, const float* B,
+                  const double* W, float* Rout, float* rowsq, hipStream_t st) {
+  const dim3 g((unsigned)((L.n + kResWG - 1) / kResWG)), t(256);
+  switch (L.dp) {
+    case 4: hipLaunchKernelGGL((k_residual<KERN, 4, NH>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, D.respart); break;
+    case 8: hipLaunchKernelGGL((k_residual<KERN, 8, NH>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, D.respart); break;
+    case 12: hipLaunchKernelGGL((k_residual<KERN, 12, NH>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, D.respart); break;
+    case 16: hipLaunchKernelGGL((k_residual<KERN, 16, NH>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, D.respart); break;
+    default: hipLaunchKernelGGL((k_residual<KERN, 20, NH>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, D.respart); break;
+  }
+}
+
 template <int KERN>
 void launch_res_k(const Layout& L, const Dev& D, const Params& P, const float* X, const float* B,
                   const double* W, float* Rout, float* rowsq, hipStream_t st) {
-  const dim3 g(L.nwg_res), t(kResRows);
-  if (L.l <= 1)
-    hipLaunchKernelGGL((k_residual<KERN, 1>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, D.respart);
-  else if (L.l <= 4)
-    hipLaunchKernelGGL((k_residual<KERN, 4>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, D.respart);
-  else if (L.l <= 8)
-    hipLaunchKernelGGL((k_residual<KERN, 8>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, D.respart);
-  else if (L.l <= 16)
-    hipLaunchKernelGGL((k_residual<KERN, 16>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, D.respart);
+  if (L.l <= 16)
+    launch_res_d<KERN, 1>(L, D, P, X, B, W, Rout, rowsq, st);
   else
-    hipLaunchKernelGGL((k_residual<KERN, 32>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, D.respart);
+    launch_res_d<KERN, 2>(L, D, P, X, B, W, Rout, rowsq, st);
 }
 
 }  // namespace

@@ -2,13 +2,21 @@
 //   delta = K^_{I,I}^{-1} R_I,  W_I += delta,
 // with the cached inverse, so the solve is one FP64 product of a b x b matrix
 // with the b x l block of the residual. The step is also written, times the
-// outputscale, in the operand layout of the fused residual update (BF16 or FP32).
+// outputscale, in the operand layout of the fused residual update: FP32, one
+// BF16 term, or three BF16 terms (h + m + l) for the split path.
 #include <algorithm>
 
 #include "ap_internal.h"
 
 namespace ap {
 namespace {
+
+__device__ inline uint16_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // Partial products over one of kBsSplit slices of the block columns q.
 // Workgroup: 64 output rows (one per lane) x LB >= l columns; the 4 waves take
@@ -81,18 +89,31 @@ __global__ __launch_bounds__(256) void k_bs_finish(Layout L, const Ctl* __restri
     W[(start + i) * L.l + c] += v;
   }
   delta[i * kMaxL + c] = v;
-  const float sv = (float)(s * v);
   if (L.tile == 0) {
-    ((float*)dtile)[i * kMaxL + c] = sv;
-  } else {
-    // bcol i of chunk ch: k-step st = w / 16; within it bcol = 4g + (e % 4) + 8 (e / 4)
-    const int ch = i / 32, w = i % 32, st = w / 16, w2 = w % 16;
-    const int g = (w2 % 8) / 4, el = (w2 / 8) * 4 + w2 % 4;
-    const int lane = g * 32 + c;
-    uint32_t u = __float_as_uint(sv);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    ((uint16_t*)dtile)[(((size_t)ch * 2 + st) * 64 + lane) * 8 + el] = (uint16_t)(u >> 16);
+    ((float*)dtile)[i * kMaxL + c] = (float)(s * v);
+    return;
   }
+  // BF16 operand layout: bcol i of chunk ch sits in k-step st = w / 16 at
+  // lane g * 32 + c, element el, where w = i % 32 = 16 st + 4 g + (el % 4) + 8 (el / 4)
+  const int ch = i / 32, w = i % 32, st = w / 16, w2 = w % 16;
+  const int g = (w2 % 8) / 4, el = (w2 / 8) * 4 + w2 % 4;
+  const int lane = g * 32 + c;
+  const size_t at = (((size_t)ch * 2 + st) * 64 + lane) * 8 + el;
+  uint16_t* out = (uint16_t*)dtile;
+  if (L.tile == 1) {
+    out[at] = bf16_rne((float)(s * v));
+    return;
+  }
+  // split path: s * delta = h + m + l, three BF16 terms (24 significant bits)
+  const size_t term = (size_t)L.b_pad * kMaxL;
+  const double sv = s * v;
+  const uint16_t h = bf16_rne((float)sv);
+  const double r1 = sv - (double)bf16_to_f32(h);
+  const uint16_t m = bf16_rne((float)r1);
+  const double r2 = r1 - (double)bf16_to_f32(m);
+  out[at] = h;
+  out[term + at] = m;
+  out[2 * term + at] = bf16_rne((float)r2);
 }
 
 }  // namespace

@@ -27,8 +27,8 @@ typedef __attribute__((ext_vector_type(2))) float f32x2;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 typedef __attribute__((ext_vector_type(16))) double f64x16;
 
-constexpr float kInvLog2e = 0.6931471805599453f;             // 1 / log2(e)
-constexpr float kInv3Log2e2 = 0.16017132519074588f;          // 1 / (3 log2(e)^2)
+constexpr float kInvLog2e = (float)(1.0 / kLog2e);                   // ln 2
+constexpr float kInv3Log2e2 = (float)(1.0 / (3.0 * kLog2e * kLog2e));  // 1 / (3 log2(e)^2)
 
 // Kernel map on the prepared squared distance. `a` is -|v_i - v_j|^2 (BF16
 // path) or |v_i - v_j|^2 (FP32 path); only its magnitude enters the Matern maps.
@@ -256,6 +256,100 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const float* __res
   epilogue(L, row0, start, len, acc, R, rowsq, colsq, want_rowsq, want_colsq);
 }
 
+// Split path: FP32 kernel tiles (exact differencing of FP32 features, FP32
+// map) and the product on BF16 matrix cores. The tile K = kh + km + kl and the
+// step d = dh + dm + dl are each held as three BF16 terms (24 significant bits),
+// and the six partial products with term orders summing to at most 2,
+//   dl kh + dh kl + dm km + dm kh + dh km + dh kh   (small to large),
+// are accumulated in FP32 per chunk and in FP64 across chunks: the product has
+// FP32-grade accuracy at BF16 matrix-core rates. The K operand of each MFMA is
+// built per lane in the BF16 path's column order, so the step layout is shared.
+template <int KERN, int DV, int DP>
+__global__ __launch_bounds__(256) void k_fused_split(Layout L, const float* __restrict__ xs,
+                                                     const uint16_t* __restrict__ dtile,
+                                                     const Ctl* __restrict__ ctl, int block,
+                                                     float* __restrict__ R,
+                                                     float* __restrict__ rowsq,
+                                                     float* __restrict__ colsq, int want_rowsq,
+                                                     int want_colsq) {
+  __shared__ float sx[kChunk][DP];
+  const int blk = block >= 0 ? block : ctl->sel;
+  const int64_t start = (int64_t)blk * L.b;
+  const int len = (int)std::min<int64_t>(L.b, L.n - start);
+  const int nch = (len + kChunk - 1) / kChunk;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int nl = lane % 32, g = lane / 32;
+  const int64_t row0 = (int64_t)blockIdx.x * kRowsWG + wave * 64;
+  const size_t term = (size_t)L.b_pad * kMaxL;
+
+  float xr[2][DV];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int k = 0; k < DV; ++k) xr[t][k] = xs[(row0 + 32 * t + nl) * DP + k];
+
+  f64x16 acc[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[t][v] = 0.0;
+
+  for (int ch = 0; ch < nch; ++ch) {
+    const int64_t cb = start + (int64_t)ch * kChunk;
+    __syncthreads();
+    for (int e = threadIdx.x; e < kChunk * DP; e += 256) {
+      const int c = e / DP, k = e % DP;
+      sx[c][k] = xs[(cb + c) * DP + k];
+    }
+    __syncthreads();
+    f32x16 part[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) part[t][v] = 0.f;
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      const size_t at = (((size_t)ch * 2 + st) * 64 + lane) * 8;
+      const bf16x8 dh = load_bf16x8(dtile + at);
+      const bf16x8 dm = load_bf16x8(dtile + term + at);
+      const bf16x8 dl = load_bf16x8(dtile + 2 * term + at);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        f32x16 kv;  // only elements 0..7 used: this k-step's eight columns
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int cc = 16 * st + 4 * g + (e % 4) + 8 * (e / 4);
+          float r2 = 0.f;
+#pragma unroll
+          for (int k = 0; k < DV; ++k) {
+            const float df = xr[t][k] - sx[cc][k];
+            r2 = fmaf(df, df, r2);
+          }
+          kv[e] = kmap_neg<KERN>(-r2);
+        }
+        const bf16x8 kh = pack8(kv, 0);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) kv[e] -= (float)kh[e];
+        const bf16x8 km = pack8(kv, 0);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) kv[e] -= (float)km[e];
+        const bf16x8 kl = pack8(kv, 0);
+        part[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(dl, kh, part[t], 0, 0, 0);
+        part[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(dh, kl, part[t], 0, 0, 0);
+        part[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(dm, km, part[t], 0, 0, 0);
+        part[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(dm, kh, part[t], 0, 0, 0);
+        part[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(dh, km, part[t], 0, 0, 0);
+        part[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(dh, kh, part[t], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[t][v] += (double)part[t][v];
+  }
+  epilogue(L, row0, start, len, acc, R, rowsq, colsq, want_rowsq, want_colsq);
+}
+
 template <int KERN>
 hipError_t launch_bf16(const Layout& L, const Dev& D, int32_t block, float* R, bool wr, bool wc,
                        hipStream_t st) {
@@ -287,6 +381,26 @@ hipError_t launch_fp32(const Layout& L, const Dev& D, int32_t block, float* R, b
   return hipGetLastError();
 }
 
+template <int KERN>
+hipError_t launch_split(const Layout& L, const Dev& D, int32_t block, float* R, bool wr,
+                        bool wc, hipStream_t st) {
+  const dim3 g(L.nwg), t(256);
+  const uint16_t* dt = (const uint16_t*)D.dtile;
+  if (L.d == 3) {
+    hipLaunchKernelGGL((k_fused_split<KERN, 3, 4>), g, t, 0, st, L, D.xs, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc);
+    return hipGetLastError();
+  }
+  switch (L.dp) {
+    case 4: hipLaunchKernelGGL((k_fused_split<KERN, 4, 4>), g, t, 0, st, L, D.xs, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 8: hipLaunchKernelGGL((k_fused_split<KERN, 8, 8>), g, t, 0, st, L, D.xs, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 12: hipLaunchKernelGGL((k_fused_split<KERN, 12, 12>), g, t, 0, st, L, D.xs, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 16: hipLaunchKernelGGL((k_fused_split<KERN, 16, 16>), g, t, 0, st, L, D.xs, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 20: hipLaunchKernelGGL((k_fused_split<KERN, 20, 20>), g, t, 0, st, L, D.xs, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_fused_update(const Layout& L, const Dev& D, int32_t block, float* R,
@@ -296,6 +410,13 @@ hipError_t launch_fused_update(const Layout& L, const Dev& D, int32_t block, flo
       case 0: return launch_bf16<0>(L, D, block, R, want_rowsq, want_colsq, st);
       case 1: return launch_bf16<1>(L, D, block, R, want_rowsq, want_colsq, st);
       default: return launch_bf16<2>(L, D, block, R, want_rowsq, want_colsq, st);
+    }
+  }
+  if (L.tile == 2) {
+    switch (L.kernel) {
+      case 0: return launch_split<0>(L, D, block, R, want_rowsq, want_colsq, st);
+      case 1: return launch_split<1>(L, D, block, R, want_rowsq, want_colsq, st);
+      default: return launch_split<2>(L, D, block, R, want_rowsq, want_colsq, st);
     }
   }
   switch (L.kernel) {
