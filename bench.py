@@ -32,12 +32,13 @@ sys.path.insert(0, ROOT)
 
 PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 MFMA
 PEAK_FP32_TFLOPS = 157.3       # MI355X dense FP32 matrix
+PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 (vector and matrix)
 PEAK_HBM_GBS = 8000.0
 # transcendental issue: 256 CUs x 32 lanes/cycle (half rate) x 2.4 GHz
 PEAK_TRANS_PER_S = 256 * 32 * 2.4e9
 
 
-TILE_NAMES = {0: "fp32", 1: "bf16", 2: "split"}
+TILE_NAMES = {0: "fp32", 1: "bf16", 2: "split", 3: "fp64"}
 
 
 def log(*a):
@@ -96,12 +97,15 @@ def main():
     ap_.add_argument("--steps", type=int, default=5)
     ap_.add_argument("--warmup", type=int, default=1)
     ap_.add_argument("--workload", default="c3")
-    ap_.add_argument("--bf16-steps", type=int, default=1)
-    ap_.add_argument("--fp32-steps", type=int, default=1)
-    ap_.add_argument("--no-bf16", action="store_true")
+    ap_.add_argument("--main", default="fp64", choices=["fp64", "split", "fp32", "bf16"])
+    ap_.add_argument("--other-steps", type=int, default=1,
+                     help="timed epochs of each other tile path (0: main path only)")
+    ap_.add_argument("--skip", default="", help="comma-separated tile paths not to run")
     ap_.add_argument("--cpu-updates", type=int, default=2)
     ap_.add_argument("--no-cpu", action="store_true")
     ap_.add_argument("--no-true-residual", action="store_true")
+    ap_.add_argument("--copy-calibration", action="store_true",
+                     help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap_.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (this solver "
@@ -113,6 +117,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        a = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": a.numel() * 4, "copies": 3}), flush=True)
+        return
     ap.load()
     t = time.perf_counter()
     w = workload(args.workload)
@@ -175,7 +187,7 @@ def main():
             if cnt:
                 log(f"[bench]   {k:14s} {sec * 1e3:10.2f} ms over {cnt} launches "
                     f"({sec / cnt * 1e6:.1f} us each)")
-        if want_true and math.isfinite(rho):
+        if want_true and math.isfinite(rho) and rho < 1e6:
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             Rt = torch.empty_like(R)
@@ -185,27 +197,37 @@ def main():
             log(f"[bench] {res['tile']}: FP64 true residual rho {res['rho_true']:.6f} in "
                 f"{res['true_residual_s']:.2f} s")
             del Rt
-        res["diverged"] = not (math.isfinite(rho) and (res.get("rho_true") is None or
-                                                       abs(res["rho_true"] - rho) < 0.1 * res["rho_true"]))
+        # the maintained residual has left B - K^ W when they differ by > 0.1%
+        res["drift"] = (abs(res["rho_true"] - rho) / res["rho_true"]
+                        if res.get("rho_true") else None)
+        res["diverged"] = not (math.isfinite(rho) and rho < 1e6 and
+                               (res["drift"] is None or res["drift"] < 1e-3))
         del s, W, R
         torch.cuda.empty_cache()
         return res
 
+    # The main path is the one whose maintained residual stays the true one on
+    # this system: FP64 kernel tiles. The FP32-grade and BF16 tile paths run
+    # after it for their epoch rates; on this workload their maintained
+    # residual drifts away from B - K^ W (reported as "diverged").
     paths = {}
-    main_tile = ap.TILE_SPLIT
-    paths["split"] = run_path(ap.TILE_SPLIT, args.steps, args.warmup, not args.no_true_residual)
-    if args.fp32_steps > 0:
-        paths["fp32"] = run_path(ap.TILE_FP32, args.fp32_steps, 0, False)
-    if not args.no_bf16:
-        paths["bf16"] = run_path(ap.TILE_BF16, args.bf16_steps, 1, False)
-    main = paths[TILE_NAMES[main_tile]]
+    main_tile = {"fp64": ap.TILE_FP64, "split": ap.TILE_SPLIT, "fp32": ap.TILE_FP32,
+                 "bf16": ap.TILE_BF16}[args.main]
+    paths[args.main] = run_path(main_tile, args.steps, args.warmup, not args.no_true_residual)
+    for name, tile, steps, warm in (("split", ap.TILE_SPLIT, args.other_steps, 1),
+                                    ("fp32", ap.TILE_FP32, args.other_steps, 1),
+                                    ("bf16", ap.TILE_BF16, args.other_steps, 1)):
+        if name != args.main and steps > 0 and name not in args.skip.split(","):
+            paths[name] = run_path(tile, steps, warm, not args.no_true_residual)
+    main = paths[args.main]
 
     upd = main["phases"]["fused_update"]
     avg = upd["s"] / upd["launches"]
     entries_per_launch = w.n * w.n / w.m  # every epoch touches n^2 kernel entries
     flops_launch = 2.0 * (w.d + w.l) * entries_per_launch
     achieved = flops_launch / avg / 1e12
-    peak = PEAK_FP32_TFLOPS if main_tile == ap.TILE_FP32 else PEAK_BF16_TFLOPS
+    peak = {ap.TILE_FP32: PEAK_FP32_TFLOPS, ap.TILE_FP64: PEAK_FP64_TFLOPS}.get(
+        main_tile, PEAK_BF16_TFLOPS)
     # the split path runs six BF16 partial products per tile entry and column
     mfma_flops_launch = flops_launch * (6 if main_tile == ap.TILE_SPLIT else 1)
     trans_rate = trans_per_entry(w.kernel) * entries_per_launch / avg
@@ -213,6 +235,7 @@ def main():
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak,
                 "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
                 "kernel": f"k_fused_{main['tile']} (fused K-tile residual update)",
+                "flops_counted": "2 (d + l) per kernel entry: x.x' and the product with the step",
                 "avg_launch_us": avg * 1e6,
                 "flops_per_entry": 2 * (w.d + w.l), "entries_per_launch": entries_per_launch,
                 "transcendental_frac": trans_rate / PEAK_TRANS_PER_S,

@@ -78,8 +78,12 @@ typedef enum { AP_CYCLIC = 0, AP_GREEDY = 1 } ap_order;
  *  AP_TILE_SPLIT: r^2 by exact differencing in FP32, kernel map in FP32, tile
  *                 and step each split into three BF16 terms and multiplied on
  *                 BF16 matrix cores (six partial products), FP32 accumulation
- *                 per 32 columns and FP64 across them: FP32-grade products. */
-typedef enum { AP_TILE_FP32 = 0, AP_TILE_BF16 = 1, AP_TILE_SPLIT = 2 } ap_tile;
+ *                 per 32 columns and FP64 across them: FP32-grade products.
+ *  AP_TILE_FP64:  kernel values in FP64 (exact differencing, FP64 map) and the
+ *                 product on FP64 matrix cores; only R is stored in FP32. For
+ *                 systems so ill-conditioned that FP32 kernel values let the
+ *                 maintained residual drift away from B - K^ W. */
+typedef enum { AP_TILE_FP32 = 0, AP_TILE_BF16 = 1, AP_TILE_SPLIT = 2, AP_TILE_FP64 = 3 } ap_tile;
 
 /* Limits of this build: 1 <= d <= 20, 1 <= l <= 32, 1 <= b <= 4096, b <= n,
  * n < 2^31. Larger sizes return AP_ERR_UNSUPPORTED. */

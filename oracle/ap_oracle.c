@@ -151,17 +151,24 @@ int64_t apo_factor_one(const apo_config* c, const double* X, int64_t j, double* 
 int64_t apo_factor(const apo_config* c, const double* X, double* L, int64_t* bad_pivot) {
   int64_t m = apo_num_blocks(c);
   int64_t bb = (int64_t)c->b * c->b;
-  int64_t first_bad = -1, first_piv = -1;
+  int64_t* piv = (int64_t*)malloc(sizeof(int64_t) * (size_t)m);
+  /* blocks are independent: one thread per block, each factor sequential */
+#pragma omp parallel for schedule(dynamic, 1)
   for (int64_t j = 0; j < m; ++j) {
     int64_t s = apo_block_start(c, j), len = apo_block_len(c, j);
     double* Lj = L + j * bb;
-    apo_khat_block(c, X, s, s + len, s, s + len, Lj);
-    int64_t piv = apo_cholesky(Lj, len);
-    if (piv >= 0 && first_bad < 0) {
-      first_bad = j;
-      first_piv = piv;
-    }
+    for (int64_t i = 0; i < len; ++i)
+      for (int64_t q = 0; q < len; ++q) Lj[i * len + q] = apo_khat(c, X, s + i, s + q);
+    piv[j] = apo_cholesky(Lj, len);
   }
+  int64_t first_bad = -1, first_piv = -1;
+  for (int64_t j = 0; j < m; ++j)
+    if (piv[j] >= 0) {
+      first_bad = j;
+      first_piv = piv[j];
+      break;
+    }
+  free(piv);
   if (bad_pivot) *bad_pivot = first_piv;
   return first_bad;
 }

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libapgp.so")
 
 RBF, MATERN32, MATERN52 = 0, 1, 2
 CYCLIC, GREEDY = 0, 1
-TILE_FP32, TILE_BF16, TILE_SPLIT = 0, 1, 2
+TILE_FP32, TILE_BF16, TILE_SPLIT, TILE_FP64 = 0, 1, 2, 3
 
 OK, NOT_CONVERGED = 0, 1
 ERR_INVALID_ARG, ERR_NOT_PD, ERR_NONFINITE = -1, -2, -3

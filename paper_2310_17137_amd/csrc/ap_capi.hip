@@ -43,7 +43,7 @@ ap_status check_config(const ap_config* c) {
   if (c->n < 1 || c->d < 1 || c->l < 1 || c->b < 1 || c->b > c->n) return AP_ERR_INVALID_ARG;
   if (c->kernel < AP_RBF || c->kernel > AP_MATERN52) return AP_ERR_INVALID_ARG;
   if (c->order != AP_CYCLIC && c->order != AP_GREEDY) return AP_ERR_INVALID_ARG;
-  if (c->tile < AP_TILE_FP32 || c->tile > AP_TILE_SPLIT) return AP_ERR_INVALID_ARG;
+  if (c->tile < AP_TILE_FP32 || c->tile > AP_TILE_FP64) return AP_ERR_INVALID_ARG;
   if (!(c->outputscale > 0.0) || !std::isfinite(c->outputscale)) return AP_ERR_INVALID_ARG;
   if (!(c->noise >= 0.0) || !std::isfinite(c->noise)) return AP_ERR_INVALID_ARG;
   if (!(c->tol >= 0.0) || std::isnan(c->tol)) return AP_ERR_INVALID_ARG;
@@ -93,7 +93,11 @@ ap_status one_update(ap_problem* h, const ap_state* st, int32_t block, bool last
                      hipStream_t s) {
   const bool greedy = h->L.order == AP_GREEDY;
   AP_PHASE(kSolve, ap::launch_block_solve(h->L, h->D, h->P, block, st->R, st->W, s));
-  AP_PHASE(kUpdate, ap::launch_fused_update(h->L, h->D, block, st->R, greedy, last, s));
+  if (h->L.tile == AP_TILE_FP64)
+    AP_PHASE(kUpdate, ap::launch_fused_update64(h->L, h->D, h->P, h->X, block, st->R, greedy,
+                                                last, s));
+  else
+    AP_PHASE(kUpdate, ap::launch_fused_update(h->L, h->D, block, st->R, greedy, last, s));
   if (greedy) AP_PHASE(kSelect, ap::launch_select(h->L, h->D, s));
   return AP_OK;
 }
@@ -242,7 +246,7 @@ ap_status ap_solve(ap_handle h, const ap_state* st, hipStream_t stream, ap_stats
   s.rho_true = NAN;
   ap_status r = ap_reset(h, st, stream);
   if (r != AP_OK) return r;
-  const bool confirm = c.refine_every > 0 || c.tile != AP_TILE_FP32;
+  const bool confirm = c.refine_every > 0 || c.tile == AP_TILE_BF16 || c.tile == AP_TILE_SPLIT;
   ap_status result = AP_NOT_CONVERGED;
   ap::Ctl ctl;
   double t_ep = 0.0, t_ref = 0.0;

@@ -95,6 +95,9 @@ hipError_t launch_block_solve(const Layout& L, const Dev& D, const Params& P, in
                               const float* R, double* W, hipStream_t st);
 hipError_t launch_fused_update(const Layout& L, const Dev& D, int32_t block, float* R,
                                bool want_rowsq, bool want_colsq, hipStream_t st);
+hipError_t launch_fused_update64(const Layout& L, const Dev& D, const Params& P, const float* X,
+                                 int32_t block, float* R, bool want_rowsq, bool want_colsq,
+                                 hipStream_t st);
 hipError_t launch_select(const Layout& L, const Dev& D, hipStream_t st);
 hipError_t launch_epoch_check(const Layout& L, const Dev& D, hipStream_t st);
 hipError_t launch_residual(const Layout& L, const Dev& D, const Params& P, const float* X,

@@ -169,6 +169,7 @@ __global__ __launch_bounds__(256) void k_prep(Layout L, Params P, const float* _
     }
     return;
   }
+  if (L.tile != 1) return;  // the FP64-tile path reads X itself
   const int kf = 16 * L.ks;
   uint16_t* r = xrow + i * kf;
   uint16_t* q = xcol + i * kf;

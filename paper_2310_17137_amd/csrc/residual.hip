@@ -7,6 +7,7 @@
 #include <algorithm>
 
 #include "ap_internal.h"
+#include "kmap64.h"
 
 namespace ap {
 namespace {
@@ -15,19 +16,6 @@ constexpr int kCols = 64;  // columns staged in LDS per step
 constexpr int kResWG = 128; // rows per workgroup: 4 waves x two 16-row tiles
 
 typedef __attribute__((ext_vector_type(4))) double f64x4;
-
-template <int KERN>
-__device__ __forceinline__ double kernel_fp64(double r2, const Params& P) {
-  if constexpr (KERN == 0) {
-    return P.s * exp(-0.5 * r2);
-  } else if constexpr (KERN == 1) {
-    double t = 1.7320508075688772 * sqrt(r2);
-    return P.s * (1.0 + t) * exp(-t);
-  } else {
-    double r = sqrt(r2), t = 2.23606797749979 * r;
-    return P.s * (1.0 + t + (5.0 / 3.0) * r2) * exp(-t);
-  }
-}
 
 // The product sum_j K^_ij W_jc runs on v_mfma_f64_16x16x4f64: per step of 4
 // columns a lane evaluates one kernel entry per row tile (row lane % 16, column
@@ -87,7 +75,7 @@ __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const floa
           const double df = (xi[t][k] - sx[jj][k]) * inv_ell[k];
           r2 = fma(df, df, r2);
         }
-        double kv = kernel_fp64<KERN>(r2, P);
+        double kv = kernel_fp64<KERN>(r2, P.s);
         if (j == row0 + 16 * t + ln) kv += P.noise;
 #pragma unroll
         for (int h = 0; h < NH; ++h)

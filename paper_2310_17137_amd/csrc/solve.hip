@@ -89,6 +89,7 @@ __global__ __launch_bounds__(256) void k_bs_finish(Layout L, const Ctl* __restri
     W[(start + i) * L.l + c] += v;
   }
   delta[i * kMaxL + c] = v;
+  if (L.tile == 3) return;  // the FP64-tile update reads delta itself
   if (L.tile == 0) {
     ((float*)dtile)[i * kMaxL + c] = (float)(s * v);
     return;

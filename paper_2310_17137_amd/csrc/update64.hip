@@ -1,0 +1,191 @@
+// Fused residual update with FP64 kernel tiles (eq. text_update_of_r):
+//   R <- R - K^_{:,I} delta,  rows of I set to 0,
+// for systems whose conditioning defeats FP32 tiles. The product K^_{:,I} delta
+// cancels to |R| from terms as large as |K||delta| (far larger when K^_{I,I} is
+// close to singular), so the rounding of the kernel values, not of R, decides
+// whether the maintained residual stays true. Here every kernel value is FP64
+// (exact differencing of the inputs over the lengthscales, FP64 map) and the
+// product runs on v_mfma_f64_16x16x4f64 with FP64 accumulation; only the stored
+// residual is FP32, whose rounding is relative to |R| itself.
+//
+// Workgroup: 4 waves x 64 rows (four 16-row tiles each), the same 256-row
+// geometry and per-workgroup column partials as the other tile modes. The
+// block's columns are staged through LDS 64 at a time (features and step); per
+// step of 4 columns a lane evaluates one kernel value per row tile (row
+// lane % 16, column lane / 16) and the matrix cores accumulate
+// acc[c][i] += delta^T[c][j] K^T[j][i] for 16 right-hand sides per half.
+#include <algorithm>
+
+#include "ap_internal.h"
+#include "kmap64.h"
+
+namespace ap {
+namespace {
+
+typedef __attribute__((ext_vector_type(4))) double f64x4;
+constexpr int kCols64 = 64;
+
+template <int KERN, int DV, int DP, int NH>
+__global__ __launch_bounds__(256) void k_fused_fp64(Layout L, Params P, const float* __restrict__ X,
+                                                    const double* __restrict__ delta,
+                                                    const Ctl* __restrict__ ctl, int block,
+                                                    float* __restrict__ R,
+                                                    float* __restrict__ rowsq,
+                                                    float* __restrict__ colsq, int want_rowsq,
+                                                    int want_colsq) {
+  __shared__ double sx[kCols64][DP];
+  __shared__ double sd[kCols64][16 * NH];
+  __shared__ float red[4][kMaxL];
+  const int blk = block >= 0 ? block : ctl->sel;
+  const int64_t start = (int64_t)blk * L.b;
+  const int len = (int)std::min<int64_t>(L.b, L.n - start);
+  const int d = L.d, l = L.l;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int ln = lane % 16, lg = lane / 16;
+  const int64_t row0 = (int64_t)blockIdx.x * kRowsWG + wave * 64;
+
+  double inv_ell[DV];
+#pragma unroll
+  for (int k = 0; k < DV; ++k) inv_ell[k] = k < d ? 1.0 / P.ell[k] : 0.0;
+  double xi[4][DV];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int64_t i = row0 + 16 * t + ln;
+#pragma unroll
+    for (int k = 0; k < DV; ++k)
+      xi[t][k] = (i < L.n && k < d) ? (double)X[i * d + k] * inv_ell[k] : 0.0;
+  }
+  f64x4 acc[4][NH];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int h = 0; h < NH; ++h) acc[t][h] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  for (int c0 = 0; c0 < len; c0 += kCols64) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < kCols64 * DP; e += 256) {
+      const int jj = e / DP, k = e % DP;
+      sx[jj][k] = (c0 + jj < len && k < d) ? (double)X[(start + c0 + jj) * d + k] / P.ell[k] : 0.0;
+    }
+    for (int e = threadIdx.x; e < kCols64 * 16 * NH; e += 256) {
+      const int jj = e / (16 * NH), c = e % (16 * NH);
+      sd[jj][c] = (c0 + jj < len) ? delta[(size_t)(c0 + jj) * kMaxL + c] : 0.0;
+    }
+    __syncthreads();
+    const int steps = std::min(kCols64, len - c0 + 3) / 4;
+    for (int st = 0; st < steps; ++st) {
+      const int jj = 4 * st + lg;
+      double a[NH];
+#pragma unroll
+      for (int h = 0; h < NH; ++h) a[h] = sd[jj][16 * h + ln];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        double r2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < DV; ++k) {
+          const double df = xi[t][k] - sx[jj][k];
+          r2 = fma(df, df, r2);
+        }
+        const double kv = kernel_fp64<KERN>(r2, P.s);
+#pragma unroll
+        for (int h = 0; h < NH; ++h)
+          acc[t][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h], kv, acc[t][h], 0, 0, 0);
+      }
+    }
+  }
+
+  // lane holds acc[t][h][q]: row row0 + 16 t + lane % 16, column c = 16 h + lane / 16 + 4 q
+  float csum[NH][4];
+#pragma unroll
+  for (int h = 0; h < NH; ++h)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) csum[h][q] = 0.f;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int64_t row = row0 + 16 * t + ln;
+    const bool live = row < L.n;
+    const bool in_i = row >= start && row < start + len;
+    float rs = 0.f;
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int c = 16 * h + lg + 4 * q;
+        if (live && c < l) {
+          const float r = in_i ? 0.f : (float)((double)R[row * l + c] - acc[t][h][q]);
+          R[row * l + c] = r;
+          rs = fmaf(r, r, rs);
+          csum[h][q] = fmaf(r, r, csum[h][q]);
+        }
+      }
+    if (want_rowsq) {
+      rs += __shfl_xor(rs, 16);
+      rs += __shfl_xor(rs, 32);
+      if (lg == 0 && row < L.n_pad) rowsq[row] = live ? rs : 0.f;
+    }
+  }
+  if (want_colsq) {
+#pragma unroll
+    for (int h = 0; h < NH; ++h)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float x = csum[h][q];
+        x += __shfl_xor(x, 1);
+        x += __shfl_xor(x, 2);
+        x += __shfl_xor(x, 4);
+        x += __shfl_xor(x, 8);
+        if (ln == 0) red[wave][16 * h + lg + 4 * q] = x;
+      }
+    __syncthreads();
+    if (threadIdx.x < kMaxL) {
+      const int c = threadIdx.x;
+      float v = 0.f;
+      if (c < 16 * NH) v = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+      colsq[blockIdx.x * kMaxL + c] = c < l ? v : 0.f;
+    }
+  }
+}
+
+template <int KERN, int NH>
+hipError_t launch_nh(const Layout& L, const Dev& D, const Params& P, const float* X, int32_t block,
+                     float* R, bool wr, bool wc, hipStream_t st) {
+  const dim3 g(L.nwg), t(256);
+#define AP_F64(DV, DP)                                                                           \
+  hipLaunchKernelGGL((k_fused_fp64<KERN, DV, DP, NH>), g, t, 0, st, L, P, X, D.delta, D.ctl, block, \
+                     R, D.rowsq, D.colsq, (int)wr, (int)wc)
+  if (L.d == 3) {
+    AP_F64(3, 4);
+  } else {
+    switch (L.dp) {
+      case 4: AP_F64(4, 4); break;
+      case 8: AP_F64(8, 8); break;
+      case 12: AP_F64(12, 12); break;
+      case 16: AP_F64(16, 16); break;
+      case 20: AP_F64(20, 20); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+#undef AP_F64
+  return hipGetLastError();
+}
+
+template <int KERN>
+hipError_t launch_k(const Layout& L, const Dev& D, const Params& P, const float* X, int32_t block,
+                    float* R, bool wr, bool wc, hipStream_t st) {
+  if (L.l <= 16) return launch_nh<KERN, 1>(L, D, P, X, block, R, wr, wc, st);
+  return launch_nh<KERN, 2>(L, D, P, X, block, R, wr, wc, st);
+}
+
+}  // namespace
+
+hipError_t launch_fused_update64(const Layout& L, const Dev& D, const Params& P, const float* X,
+                                 int32_t block, float* R, bool want_rowsq, bool want_colsq,
+                                 hipStream_t st) {
+  switch (L.kernel) {
+    case 0: return launch_k<0>(L, D, P, X, block, R, want_rowsq, want_colsq, st);
+    case 1: return launch_k<1>(L, D, P, X, block, R, want_rowsq, want_colsq, st);
+    default: return launch_k<2>(L, D, P, X, block, R, want_rowsq, want_colsq, st);
+  }
+}
+
+}  // namespace ap

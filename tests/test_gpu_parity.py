@@ -195,6 +195,54 @@ def test_epochs_split_match_oracle(case):
 
 
 @pytest.mark.parametrize("case", CASES)
+def test_epochs_fp64_tiles_match_oracle(case):
+    """FP64 kernel tiles: only the stored residual is FP32, so the iterates stay
+    within 1e-5 of the oracle's whatever the conditioning."""
+    w = _small(case)
+    s, B, W, R = _gpu(w, tile=ap.TILE_FP64)
+    s.reset(B, W, R)
+    p = to_oracle(w)
+    L = apo.factor(p)
+    Wo, Ro = np.zeros_like(p.B), p.B.copy()
+    for ep in range(3):
+        s.epoch(B, W, R, 1)
+        apo.epoch(p, L, Wo, Ro)
+        rho, _ = s.rel_residual()
+        e = _rel(W.cpu().numpy(), Wo)
+        print(f"[fp64] epoch {ep + 1} W err {e:.3e}", flush=True)
+        assert e < 1e-5, ep
+        rho_o = apo.rel_residual(p, Ro)
+        assert abs(rho - rho_o) <= max(1e-5 * rho_o, 1e-7)
+
+
+def test_c3_generator_fp64_tiles_track_oracle():
+    """The ill-conditioned n = 2M recipe at n = 32768 (64-cluster mixture, RBF
+    lengthscale 0.1, sigma^2 = 1e-4, b = 2048, 32 right-hand sides): FP64 tiles
+    follow the oracle's iterates over 3 epochs, and the maintained residual
+    stays the true one."""
+    w = gen.c3(n=32768)
+    s, B, W, R = _gpu(w, tile=ap.TILE_FP64)
+    s.reset(B, W, R)
+    p = to_oracle(w)
+    L = apo.factor(p)
+    Wo, Ro = np.zeros_like(p.B), p.B.copy()
+    for ep in range(3):
+        s.epoch(B, W, R, 1)
+        apo.epoch(p, L, Wo, Ro)
+        rho, _ = s.rel_residual()
+        e = _rel(W.cpu().numpy(), Wo)
+        rho_o = apo.rel_residual(p, Ro)
+        print(f"[c3-32k] epoch {ep + 1} rho {rho:.6f} oracle {rho_o:.6f} W err {e:.3e}", flush=True)
+        assert abs(rho - rho_o) <= 1e-4 * rho_o
+        assert e < 1e-3
+    Rt = torch.empty_like(R)
+    cols = s.residual(B, W, R, R_out=Rt)
+    drift = float((R - Rt).norm() / Rt.norm())
+    print(f"[c3-32k] maintained vs true residual {drift:.3e}", flush=True)
+    assert drift < 1e-4
+
+
+@pytest.mark.parametrize("case", CASES)
 def test_single_update_bf16(case):
     w = _small(case)
     s, B, W, R = _gpu(w, tile=ap.TILE_BF16)
@@ -339,12 +387,15 @@ def test_nonfinite_rhs_is_reported():
 
 
 @pytest.mark.parametrize("kern", [apo.RBF, apo.MATERN32, apo.MATERN52])
-@pytest.mark.parametrize("tile", [ap.TILE_FP32, ap.TILE_SPLIT, ap.TILE_BF16])
+@pytest.mark.parametrize("tile", [ap.TILE_FP32, ap.TILE_SPLIT, ap.TILE_BF16, ap.TILE_FP64])
 def test_kernel_column_through_unit_blocks(kern, tile):
     """With b = 1 every block is one point j, the step is R_j / (s + sigma^2)
     and one update subtracts that step times the kernel column k(x_:, x_j): the
-    change of R reads out the GPU's kernel values one column at a time. FP32
-    and split tiles: within 8 FP32 ulps of |R| + |k delta|; BF16 tiles: 2^-7."""
+    change of R reads out the GPU's kernel values one column at a time.
+    FP32-grade tiles: a kernel value computed from an FP32 exponent argument
+    carries that argument's relative error times |ln(k/s)| (the condition
+    number of exp), so the bound is u32 (4 |R| + (4 + 4 |ln(k/s)|) |k delta|);
+    FP64 tiles meet the same bound with room; BF16 tiles: 2^-7 |R| + |k delta|."""
     rng = np.random.default_rng(11)
     w = gen.small(12, 1500, 5, 3, 1, kernel=kern, noise=0.05,
                   ell=rng.uniform(0.15, 0.6, size=5), outputscale=1.7)
@@ -360,8 +411,14 @@ def test_kernel_column_through_unit_blocks(kern, tile):
         s.update(B, W, R, j)
         torch.cuda.synchronize()
         Rg = R.cpu().numpy().astype(np.float64)
-        mag = np.abs(R0) + np.abs(K[:, j:j + 1]) * np.abs(delta)
-        rel = 8 * U32 if tile != ap.TILE_BF16 else 2.0 ** -7
+        kcol = np.abs(K[:, j:j + 1])
+        kcol_noiseless = kcol.copy()
+        kcol_noiseless[j] -= p.noise
+        cond = np.abs(np.log(np.maximum(kcol_noiseless / p.outputscale, 1e-300)))
+        if tile == ap.TILE_BF16:
+            rel, mag = 2.0 ** -7, np.abs(R0) + kcol * np.abs(delta)
+        else:
+            rel, mag = U32, 4 * np.abs(R0) + (4 + 4 * cond) * kcol * np.abs(delta)
         err = np.abs(Rg - Ro)
         err[j] = 0.0  # the selected row is zeroed by both
         print(f"[column] kern {kern} tile {tile} j {j}: worst err/bound "
