@@ -120,6 +120,8 @@ typedef struct {
   double rho_true;            /* the same for B - K^ W in FP64 (NaN if not computed) */
   double t_epochs;            /* seconds in epochs (HIP events) */
   double t_refine;            /* seconds in true-residual passes */
+  int32_t tile;               /* ap_tile in use when the solve ended */
+  int32_t escalated_at;       /* epoch after which FP64 tiles took over, -1 if never */
 } ap_stats;
 
 typedef struct ap_problem* ap_handle;
@@ -152,6 +154,11 @@ ap_status ap_reset(ap_handle h, const ap_state* st, hipStream_t stream);
 ap_status ap_epoch(const ap_handle* h, const ap_state* st, int32_t count, int32_t epochs,
                    hipStream_t stream);
 
+/* Switch the fused update of this handle to `tile`: AP_TILE_FP64 from any
+ * mode, or back to the mode it was created with (AP_ERR_INVALID_ARG
+ * otherwise). The cached factors do not depend on the mode. */
+ap_status ap_set_tile(ap_handle h, int32_t tile);
+
 /* One block update on block `block` (0 <= block < m): the inner loop body of
  * Algorithm 1. Asynchronous. */
 ap_status ap_update(ap_handle h, const ap_state* st, int32_t block, hipStream_t stream);
@@ -164,9 +171,13 @@ ap_status ap_rel_residual(ap_handle h, hipStream_t stream, double* rho, double* 
 
 /* Algorithm 1 with the stopping rule: reset, then epochs until rho < tol with
  * at least min_epochs epochs, or max_epochs. Every refine_every epochs, and on
- * a tolerance hit when refine_every > 0 or tile == AP_TILE_BF16, R is replaced
- * by the FP64 true residual (which is exact by Lemma residual_equality) and the
- * test is repeated on it. Synchronizes once per epoch. Returns AP_OK,
+ * a tolerance hit when refine_every > 0 or the tile mode is not FP32, R is
+ * replaced by the FP64 true residual (exact by Lemma residual_equality) and the
+ * test is repeated on it. If that true residual's ratio and the maintained one
+ * differ by more than 5%, the rest of the solve runs on FP64 tiles from the
+ * current W; if an epoch's norms are not finite, the solve restarts from W = 0
+ * on FP64 tiles (stats.tile, stats.escalated_at). The handle's own mode is
+ * unchanged afterwards. Synchronizes once per epoch. Returns AP_OK,
  * AP_NOT_CONVERGED or an error; out [host, may be NULL] gets the statistics. */
 ap_status ap_solve(ap_handle h, const ap_state* st, hipStream_t stream, ap_stats* out);
 

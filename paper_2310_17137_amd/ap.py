@@ -26,7 +26,8 @@ ERR_WORKSPACE, ERR_HIP, ERR_UNSUPPORTED = -4, -5, -6
 
 # every symbol include/ap.h declares
 SYMBOLS = ("ap_workspace_bytes", "ap_factor_blocks", "ap_reset", "ap_epoch", "ap_update",
-           "ap_rel_residual", "ap_solve", "ap_residual", "ap_block_inverse", "ap_profile",
+           "ap_rel_residual", "ap_solve", "ap_residual", "ap_block_inverse", "ap_set_tile",
+           "ap_profile",
            "ap_profile_read", "ap_destroy", "ap_status_str")
 PHASES = ("block_solve", "fused_update", "select", "epoch_check", "true_residual")
 
@@ -48,7 +49,8 @@ class State(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("epochs", ctypes.c_int32), ("refines", ctypes.c_int32),
                 ("rho_maintained", ctypes.c_double), ("rho_true", ctypes.c_double),
-                ("t_epochs", ctypes.c_double), ("t_refine", ctypes.c_double)]
+                ("t_epochs", ctypes.c_double), ("t_refine", ctypes.c_double),
+                ("tile", ctypes.c_int32), ("escalated_at", ctypes.c_int32)]
 
 
 class ApError(RuntimeError):
@@ -82,6 +84,7 @@ def load():
             "ap_solve": (I32, [P, S, P, St]),
             "ap_residual": (I32, [P, S, P, D, P]),
             "ap_block_inverse": (I32, [P, I32, P, P]),
+            "ap_set_tile": (I32, [P, I32]),
             "ap_profile": (I32, [P, I32]),
             "ap_profile_read": (I32, [P, P, D, ctypes.POINTER(I64)]),
             "ap_destroy": (None, [P]),
@@ -135,6 +138,8 @@ class SolveStats:
     rho_true: float
     t_epochs: float
     t_refine: float
+    tile: int = 0
+    escalated_at: int = -1
 
     @property
     def converged(self) -> bool:
@@ -225,7 +230,7 @@ class Solver:
         code = load().ap_solve(self.handle, ctypes.byref(st), _stream(stream), ctypes.byref(s))
         _check(code, "ap_solve", ok=(OK, NOT_CONVERGED))
         return SolveStats(code, s.epochs, s.refines, s.rho_maintained, s.rho_true, s.t_epochs,
-                          s.t_refine)
+                          s.t_refine, s.tile, s.escalated_at)
 
     def residual(self, B, W, R, R_out=None, want_col_rel: bool = True, stream=None):
         """FP64 true residual into R_out (None: refine R in place)."""
@@ -237,6 +242,9 @@ class Solver:
         if cols is None:
             return None
         return np.array(cols[:], dtype=np.float64)
+
+    def set_tile(self, tile: int):
+        _check(load().ap_set_tile(self.handle, int(tile)), "ap_set_tile")
 
     def profile(self, enable: bool = True):
         _check(load().ap_profile(self.handle, int(bool(enable))), "ap_profile")

@@ -23,6 +23,11 @@ struct ap_problem {
   bool prof = false;
   std::vector<hipEvent_t> pool[5];
   size_t used[5] = {0, 0, 0, 0, 0};
+  // one epoch's launches captured as a HIP graph, replayed on the caller's
+  // stream; re-captured when the state buffers or the tile mode change
+  hipStream_t cap = nullptr;
+  hipGraphExec_t epoch_exec = nullptr;
+  const void* key[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -108,13 +113,47 @@ ap_status refine(ap_problem* h, const ap_state* st, hipStream_t s) {
   return AP_OK;
 }
 
-ap_status run_epoch(ap_problem* h, const ap_state* st, hipStream_t s) {
+ap_status enqueue_epoch(ap_problem* h, const ap_state* st, hipStream_t s) {
   const bool greedy = h->L.order == AP_GREEDY;
   for (int32_t u = 0; u < h->L.m; ++u) {
     ap_status r = one_update(h, st, greedy ? -1 : u, u == h->L.m - 1, s);
     if (r != AP_OK) return r;
   }
   AP_PHASE(kCheck, ap::launch_epoch_check(h->L, h->D, s));
+  return AP_OK;
+}
+
+void drop_graph(ap_problem* h) {
+  if (h->epoch_exec) (void)hipGraphExecDestroy(h->epoch_exec);
+  h->epoch_exec = nullptr;
+}
+
+// An epoch is the same launch sequence every time (cyclic blocks by index,
+// greedy blocks read from the control block), so it is captured once as a
+// graph and replayed; with profiling on, the launches go out one by one.
+ap_status run_epoch(ap_problem* h, const ap_state* st, hipStream_t s) {
+  if (h->prof) return enqueue_epoch(h, st, s);
+  const void* key[4] = {st->B, st->W, st->R, (const void*)(intptr_t)(h->L.tile + 1)};
+  if (!h->epoch_exec || std::memcmp(key, h->key, sizeof(key)) != 0) {
+    drop_graph(h);
+    if (!h->cap) AP_HIP(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
+    AP_HIP(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    ap_status r = enqueue_epoch(h, st, h->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(h->cap, &g);
+    if (r != AP_OK || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return r != AP_OK ? r : AP_ERR_HIP;
+    }
+    e = hipGraphInstantiate(&h->epoch_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      h->epoch_exec = nullptr;
+      return AP_ERR_HIP;
+    }
+    std::memcpy(h->key, key, sizeof(key));
+  }
+  AP_HIP(hipGraphLaunch(h->epoch_exec, s));
   return AP_OK;
 }
 
@@ -244,9 +283,9 @@ ap_status ap_solve(ap_handle h, const ap_state* st, hipStream_t stream, ap_stats
   const ap_config& c = h->cfg;
   ap_stats s{};
   s.rho_true = NAN;
+  s.escalated_at = -1;
   ap_status r = ap_reset(h, st, stream);
   if (r != AP_OK) return r;
-  const bool confirm = c.refine_every > 0 || c.tile == AP_TILE_BF16 || c.tile == AP_TILE_SPLIT;
   ap_status result = AP_NOT_CONVERGED;
   ap::Ctl ctl;
   double t_ep = 0.0, t_ref = 0.0;
@@ -255,49 +294,71 @@ ap_status ap_solve(ap_handle h, const ap_state* st, hipStream_t stream, ap_stats
     r = run_epoch(h, st, stream);
     if (r != AP_OK) return r;
     AP_HIP(hipEventRecord(h->ev[1], stream));
-    bool refined = false;
-    if (c.refine_every > 0 && t % c.refine_every == 0) {
-      r = refine(h, st, stream);
-      if (r != AP_OK) return r;
-      refined = true;
-      s.refines++;
-    }
-    AP_HIP(hipEventRecord(h->ev[2], stream));
     r = read_ctl(h, stream, &ctl);
     if (r != AP_OK) return r;
+    if (ctl.status != 0 || !std::isfinite(ctl.rho)) {
+      // a reduced-precision tile mode overflowed, so W may hold non-finite
+      // steps: restart Algorithm 1 (W = 0, R = B) on FP64 tiles, or give up if
+      // already there
+      if (h->L.tile == AP_TILE_FP64) return AP_ERR_NONFINITE;
+      h->L.tile = AP_TILE_FP64;
+      s.escalated_at = t;
+      r = ap_reset(h, st, stream);
+      if (r != AP_OK) return r;
+      s.epochs = t;
+      s.rho_maintained = 1.0;
+      continue;
+    }
     float ms = 0.f;
     AP_HIP(hipEventElapsedTime(&ms, h->ev[0], h->ev[1]));
     t_ep += ms * 1e-3;
-    AP_HIP(hipEventElapsedTime(&ms, h->ev[1], h->ev[2]));
-    t_ref += ms * 1e-3;
-    if (ctl.status != 0 || !std::isfinite(ctl.rho)) return AP_ERR_NONFINITE;
     s.epochs = t;
     s.rho_maintained = ctl.rho;
-    double rho = refined ? ctl.rho_true : ctl.rho;
-    if (refined) s.rho_true = ctl.rho_true;
-    if (rho < c.tol && t >= c.min_epochs) {
-      if (confirm && !refined) {
-        AP_HIP(hipEventRecord(h->ev[1], stream));
-        r = refine(h, st, stream);
-        if (r != AP_OK) return r;
-        AP_HIP(hipEventRecord(h->ev[2], stream));
-        r = read_ctl(h, stream, &ctl);
-        if (r != AP_OK) return r;
-        AP_HIP(hipEventElapsedTime(&ms, h->ev[1], h->ev[2]));
-        t_ref += ms * 1e-3;
-        s.refines++;
-        s.rho_true = ctl.rho_true;
-        if (ctl.status != 0) return AP_ERR_NONFINITE;
-        if (!(ctl.rho_true < c.tol)) continue;  // the true residual says go on
+    const bool scheduled = c.refine_every > 0 && t % c.refine_every == 0;
+    const bool hit = ctl.rho < c.tol && t >= c.min_epochs;
+    const bool check = scheduled || (hit && (c.refine_every > 0 || h->L.tile != AP_TILE_FP32));
+    double rho = ctl.rho;
+    if (check) {
+      // FP64 true residual replaces R (Lemma residual_equality); when it and
+      // the maintained residual disagree by more than 5%, the remaining
+      // epochs run on FP64 tiles
+      const double maintained = ctl.rho;
+      AP_HIP(hipEventRecord(h->ev[1], stream));
+      r = refine(h, st, stream);
+      if (r != AP_OK) return r;
+      AP_HIP(hipEventRecord(h->ev[2], stream));
+      r = read_ctl(h, stream, &ctl);
+      if (r != AP_OK) return r;
+      AP_HIP(hipEventElapsedTime(&ms, h->ev[1], h->ev[2]));
+      t_ref += ms * 1e-3;
+      s.refines++;
+      if (ctl.status != 0 || !std::isfinite(ctl.rho_true)) return AP_ERR_NONFINITE;
+      s.rho_true = ctl.rho_true;
+      rho = ctl.rho_true;
+      if (h->L.tile != AP_TILE_FP64 &&
+          std::fabs(ctl.rho_true - maintained) > 0.05 * ctl.rho_true) {
+        h->L.tile = AP_TILE_FP64;
+        s.escalated_at = t;
       }
+    }
+    if (rho < c.tol && t >= c.min_epochs) {
       result = AP_OK;
       break;
     }
   }
   s.t_epochs = t_ep;
   s.t_refine = t_ref;
+  s.tile = h->L.tile;
+  h->L.tile = h->cfg.tile;  // the handle keeps its configured mode
   if (out) *out = s;
   return result;
+}
+
+ap_status ap_set_tile(ap_handle h, int32_t tile) {
+  if (!valid_handle(h)) return AP_ERR_INVALID_ARG;
+  if (tile != h->cfg.tile && tile != AP_TILE_FP64) return AP_ERR_INVALID_ARG;
+  h->L.tile = tile;
+  return AP_OK;
 }
 
 ap_status ap_block_inverse(ap_handle h, int32_t j, double* dst, hipStream_t stream) {
@@ -330,6 +391,8 @@ ap_status ap_profile_read(ap_handle h, hipStream_t stream, double* seconds, int6
 
 void ap_destroy(ap_handle h) {
   if (!h) return;
+  drop_graph(h);
+  if (h->cap) (void)hipStreamDestroy(h->cap);
   for (int i = 0; i < 4; ++i)
     if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
   for (int p = 0; p < 5; ++p)

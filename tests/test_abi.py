@@ -58,7 +58,7 @@ def test_workspace_holds_the_block_inverses():
 
 @pytest.mark.parametrize("over", [
     dict(n=0), dict(d=0), dict(l=0), dict(b=0), dict(b=20000), dict(kernel=7), dict(order=3),
-    dict(tile=2), dict(outputscale=0.0), dict(noise=-1.0), dict(lengthscale=0.0),
+    dict(tile=4), dict(tile=-1), dict(outputscale=0.0), dict(noise=-1.0), dict(lengthscale=0.0),
     dict(lengthscale=float("nan")), dict(tol=-1.0), dict(max_epochs=0), dict(min_epochs=-1),
     dict(refine_every=-2),
 ])

@@ -425,3 +425,43 @@ def test_kernel_column_through_unit_blocks(kern, tile):
               f"{np.max(err / (rel * mag)):.3f}", flush=True)
         assert np.all(err <= rel * mag)
         R.copy_(torch.from_numpy(Ro.astype(np.float32)).cuda())  # same start for the next column
+
+
+@pytest.mark.parametrize("order", [apo.CYCLIC, apo.GREEDY])
+def test_graph_replay_equals_eager_launches(order):
+    """Epochs replay a captured HIP graph; with profiling on the same launches
+    go out one by one. Every replay, with eager work and synchronizations in
+    between, gives bitwise the same W and R as the eager epochs."""
+    w = _small(CASES[1], order=order)
+    sg, B, Wg, Rg = _gpu(w, tile=ap.TILE_SPLIT)
+    se, _, We, Re = _gpu(w, tile=ap.TILE_SPLIT)
+    se.profile(True)
+    sg.reset(B, Wg, Rg)
+    se.reset(B, We, Re)
+    for ep in range(4):
+        sg.epoch(B, Wg, Rg, 1)
+        se.epoch(B, We, Re, 1)
+        torch.cuda.synchronize()
+        _ = (Wg.sum() + We.sum()).item()  # eager work between replays
+        assert torch.equal(Wg, We), ep
+        assert torch.equal(Rg, Re), ep
+        assert sg.rel_residual()[0] == se.rel_residual()[0]
+
+
+def test_solve_escalates_to_fp64_tiles():
+    """BF16 tiles on the ill-conditioned cluster recipe (n = 16384): an FP64
+    true residual finds the maintained one off by more than 5% (or not finite),
+    the rest of the solve runs on FP64 tiles, and from then on the maintained
+    residual stays the true one."""
+    w = gen.c3(n=16384, l=8)
+    w.refine_every, w.max_epochs = 2, 6
+    s, B, W, R = _gpu(w, tile=ap.TILE_BF16)
+    st = s.solve(B, W, R)
+    print(f"[escalate] {st}", flush=True)
+    assert st.tile == ap.TILE_FP64 and 1 <= st.escalated_at <= 2
+    assert np.isfinite(st.rho_true) and np.isfinite(st.rho_maintained)
+    Rt = torch.empty_like(R)
+    s.residual(B, W, R, R_out=Rt)
+    drift = float((R - Rt).norm() / Rt.norm())
+    print(f"[escalate] maintained vs true after the solve {drift:.3e}", flush=True)
+    assert drift < 1e-4
