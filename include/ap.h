@@ -29,7 +29,8 @@
  *    stated otherwise.
  *  - Work is enqueued on the given HIP stream in stream order. Only
  *    ap_factor_blocks, ap_solve, ap_rel_residual and ap_residual with a non-NULL
- *    col_rel synchronize that stream. A handle is used by one host thread at a
+ *    col_rel synchronize that stream (ap_batch_peek synchronizes a stream of
+ *    its own). A handle is used by one host thread at a
  *    time, and calls that overlap on one handle race.
  *  - Errors the device detects (a non-positive pivot, a non-finite residual)
  *    are kept in a status word in the workspace and reported by the next
@@ -202,11 +203,71 @@ ap_status ap_profile(ap_handle h, int32_t enable);
  * seconds [host, 5] and launches [host, 5], in the phase order above. */
 ap_status ap_profile_read(ap_handle h, hipStream_t stream, double* seconds, int64_t* launches);
 
+/* ---- Batch steps: many problems advanced together (continuous batching) ----
+ *
+ * A batch step gives every problem of a group its next block update of
+ * Algorithm 1 (the problems may differ in n, d, l, b, kernel, hyperparameters
+ * and tile mode) in grouped launches: one launch for the block solves of all of
+ * them, one for the fused updates of all problems on AP_TILE_SPLIT (one launch
+ * per problem on another mode), and one that advances every problem's cursor and,
+ * after the last block of an epoch, runs its epoch-end check. The epoch state
+ * lives on the device, so the host does not wait between steps. After the
+ * check a problem is held (its updates become no-ops) while the host has to act:
+ *  AP_HOLD_REFINE     epoch % refine_every == 0 (an FP64 true residual is due),
+ *  AP_HOLD_TOL        rho < tol with at least min_epochs epochs,
+ *  AP_HOLD_MAX        epoch == max_epochs,
+ *  AP_HOLD_NONFINITE  the norms were not finite.
+ * The host reads the state with ap_batch_peek, acts (for instance ap_residual
+ * to replace R by the true residual and test it, ap_set_tile, ap_reset) and
+ * resumes the problem with ap_batch_release. A problem's arithmetic depends
+ * only on its own data and these decisions, never on the rest of the group or
+ * on when the host acted: its results are bitwise those of the same problem
+ * run alone. Each problem must have been ap_reset first. */
+typedef enum {
+  AP_RUN = 0,
+  AP_HOLD_REFINE = 1,
+  AP_HOLD_TOL = 2,
+  AP_HOLD_MAX = 3,
+  AP_HOLD_NONFINITE = 4
+} ap_batch_state;
+
+typedef struct {
+  int32_t state;     /* ap_batch_state */
+  int32_t epoch;     /* epochs completed since ap_reset */
+  int32_t cursor;    /* block updates done in the current epoch */
+  int32_t status;    /* 0, or AP_ERR_NONFINITE when the last check saw NaN/Inf */
+  double rho;        /* maintained ratio after the last epoch */
+  double rho_true;   /* ratio of the last FP64 true residual (ap_residual) */
+} ap_progress;
+
+/* Enqueue `steps` batch steps of the `count` problems (h[i], st[i]), 1 <= count
+ * <= 32, each handle at most once; all on `stream`, asynchronous. Every buffer
+ * of every problem must stay allocated until the work completes. */
+ap_status ap_batch_step(const ap_handle* h, const ap_state* st, int32_t count, int32_t steps,
+                        hipStream_t stream);
+
+/* Snapshot of a problem's progress, read on a stream of the handle's own (it
+ * does not wait for work queued on other streams). The state of a held problem
+ * and every value written before it was held are exact; a running problem's
+ * fields may be mid-update. The first call allocates a small pinned host
+ * buffer and a stream, freed by ap_destroy. Synchronizes that stream only. */
+ap_status ap_batch_peek(ap_handle h, ap_progress* out);
+
+/* Resume a held problem from the next batch step (stream order). */
+ap_status ap_batch_release(ap_handle h, hipStream_t stream);
+
 /* Free the host-side handle. The caller frees X and the workspace afterwards. */
 void ap_destroy(ap_handle h);
 
 /* Static description of a status code. */
 const char* ap_status_str(ap_status s);
+
+/* Description of the last HIP failure behind an AP_ERR_HIP on the calling
+ * thread: the failing call and the HIP error name ("" if none). Entry points
+ * that launch work first take off an error that an earlier HIP call outside
+ * the library left unread, so that it is not reported as theirs; the text then
+ * records that error. Valid until the next call on this thread. */
+const char* ap_last_error(void);
 
 #ifdef __cplusplus
 }

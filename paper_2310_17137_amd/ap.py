@@ -28,7 +28,8 @@ ERR_WORKSPACE, ERR_HIP, ERR_UNSUPPORTED = -4, -5, -6
 SYMBOLS = ("ap_workspace_bytes", "ap_factor_blocks", "ap_reset", "ap_epoch", "ap_update",
            "ap_rel_residual", "ap_solve", "ap_residual", "ap_block_inverse", "ap_set_tile",
            "ap_profile",
-           "ap_profile_read", "ap_destroy", "ap_status_str")
+           "ap_profile_read", "ap_batch_step", "ap_batch_peek", "ap_batch_release",
+           "ap_destroy", "ap_status_str", "ap_last_error")
 PHASES = ("block_solve", "fused_update", "select", "epoch_check", "true_residual")
 
 
@@ -53,8 +54,20 @@ class Stats(ctypes.Structure):
                 ("tile", ctypes.c_int32), ("escalated_at", ctypes.c_int32)]
 
 
+# ap_batch_state: why a problem of a batch is held
+RUN, HOLD_REFINE, HOLD_TOL, HOLD_MAX, HOLD_NONFINITE = 0, 1, 2, 3, 4
+
+
+class Progress(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("epoch", ctypes.c_int32),
+                ("cursor", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("rho", ctypes.c_double), ("rho_true", ctypes.c_double)]
+
+
 class ApError(RuntimeError):
     def __init__(self, code: int, what: str, extra: str = ""):
+        if code == ERR_HIP:
+            extra += f" [{last_error()}]"
         super().__init__(f"{what}: {status_str(code)} ({code}){extra}")
         self.code = code
 
@@ -62,14 +75,40 @@ class ApError(RuntimeError):
 _lib = None
 
 
+def _hip_runtimes() -> set[str]:
+    """Files of the HIP runtime mapped into this process (Linux)."""
+    found = set()
+    try:
+        with open("/proc/self/maps") as fh:
+            for line in fh:
+                path = line.split()[-1] if len(line.split()) >= 6 else ""
+                if os.path.basename(path).startswith("libamdhip64.so"):
+                    found.add(os.path.realpath(path))
+    except OSError:
+        pass
+    return found
+
+
 def load():
-    """Load libapgp.so and declare its signatures (no GPU work)."""
+    """Load libapgp.so and declare its signatures (no GPU work).
+
+    The library must share PyTorch's HIP runtime: the streams and device
+    memory it is handed come from torch. torch's libraries ask for the
+    unversioned libamdhip64.so next to them, the library for libamdhip64.so.7;
+    when torch is loaded first the loader resolves the library's request to
+    torch's copy by its soname, so torch is imported before the library, and a
+    second runtime in the process is an error."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_2310_17137_amd.build`")
+        import torch  # noqa: F401  (maps torch's HIP runtime first)
         lib = ctypes.CDLL(LIB_PATH)
+        runtimes = _hip_runtimes()
+        if len(runtimes) > 1:
+            raise RuntimeError("two HIP runtimes are loaded in this process "
+                               f"({', '.join(sorted(runtimes))}); libapgp.so must share torch's")
         P, I32, I64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         C, S, St = ctypes.POINTER(Config), ctypes.POINTER(State), ctypes.POINTER(Stats)
         D = ctypes.POINTER(ctypes.c_double)
@@ -87,8 +126,12 @@ def load():
             "ap_set_tile": (I32, [P, I32]),
             "ap_profile": (I32, [P, I32]),
             "ap_profile_read": (I32, [P, P, D, ctypes.POINTER(I64)]),
+            "ap_batch_step": (I32, [ctypes.POINTER(P), S, I32, I32, P]),
+            "ap_batch_peek": (I32, [P, ctypes.POINTER(Progress)]),
+            "ap_batch_release": (I32, [P, P]),
             "ap_destroy": (None, [P]),
             "ap_status_str": (ctypes.c_char_p, [I32]),
+            "ap_last_error": (ctypes.c_char_p, []),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -100,6 +143,11 @@ def load():
 
 def status_str(code: int) -> str:
     return load().ap_status_str(code).decode()
+
+
+def last_error() -> str:
+    """The library's description of the last HIP failure on this thread."""
+    return load().ap_last_error().decode()
 
 
 def _check(code: int, what: str, ok=(OK,)):
@@ -255,6 +303,15 @@ class Solver:
         _check(load().ap_profile_read(self.handle, _stream(stream), secs, cnt), "ap_profile_read")
         return {name: (secs[i], int(cnt[i])) for i, name in enumerate(PHASES)}
 
+    def peek(self) -> Progress:
+        """Snapshot of this problem's batch progress (ap_batch_peek)."""
+        out = Progress()
+        _check(load().ap_batch_peek(self.handle, ctypes.byref(out)), "ap_batch_peek")
+        return out
+
+    def release(self, stream=None):
+        _check(load().ap_batch_release(self.handle, _stream(stream)), "ap_batch_release")
+
     def block_inverse(self, j: int, stream=None):
         import torch
         ln = min(self.b, self.n - j * self.b)
@@ -270,6 +327,14 @@ def epoch_many(solvers, states, epochs: int = 1, stream=None):
     hs = (ctypes.c_void_p * count)(*[s.handle.value for s in solvers])
     sts = (State * count)(*[Solver.cstate(*st) for st in states])
     _check(load().ap_epoch(hs, sts, count, int(epochs), _stream(stream)), "ap_epoch")
+
+
+def batch_step(solvers, states, steps: int = 1, stream=None):
+    """ap_batch_step over the problems (states: (B, W, R) tuples)."""
+    count = len(solvers)
+    hs = (ctypes.c_void_p * count)(*[s.handle.value for s in solvers])
+    sts = (State * count)(*[Solver.cstate(*st) for st in states])
+    _check(load().ap_batch_step(hs, sts, count, int(steps), _stream(stream)), "ap_batch_step")
 
 
 def from_workload(w, device="cuda", tile=TILE_FP32, **over):

@@ -2,6 +2,7 @@
 // argument validation, workspace layout, launch sequencing and status codes.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -28,16 +29,44 @@ struct ap_problem {
   hipStream_t cap = nullptr;
   hipGraphExec_t epoch_exec = nullptr;
   const void* key[4] = {nullptr, nullptr, nullptr, nullptr};
+  // batch steps: the descriptor grouped launches read (host copy and its place
+  // in the workspace), and a stream plus pinned buffer for progress snapshots
+  ap::Desc desc;
+  ap::Desc* desc_dev = nullptr;
+  hipStream_t peek_stream = nullptr;
+  ap::Ctl* peek_buf = nullptr;
 };
 
 namespace {
 
-ap_status hip_fail(hipError_t e) { return e == hipSuccess ? AP_OK : AP_ERR_HIP; }
+// Description of the last HIP failure on this thread (ap_last_error).
+thread_local char g_last_error[256] = "";
 
-#define AP_HIP(call)                         \
-  do {                                       \
-    hipError_t e_ = (call);                  \
-    if (e_ != hipSuccess) return AP_ERR_HIP; \
+ap_status note_hip(hipError_t e, const char* where) {
+  if (e == hipSuccess) return AP_OK;
+  std::snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", where, hipGetErrorName(e),
+                (int)e);
+  return AP_ERR_HIP;
+}
+
+// The launchers check their launches with hipGetLastError, which also returns
+// an error that an earlier HIP call elsewhere in the process left unread. Such
+// an error is not this library's: it is taken off (and kept for ap_last_error)
+// before the library launches anything.
+void clear_foreign_error() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess)
+    std::snprintf(g_last_error, sizeof(g_last_error),
+                  "discarded an unread error left by an earlier HIP call outside this library: "
+                  "%s (%d)", hipGetErrorName(e), (int)e);
+}
+
+#define hip_fail(call) note_hip((call), #call)
+
+#define AP_HIP(call)                                      \
+  do {                                                    \
+    hipError_t e_ = (call);                               \
+    if (e_ != hipSuccess) return note_hip(e_, #call);     \
   } while (0)
 
 // Checks every scalar field of the configuration. Returns AP_OK,
@@ -143,13 +172,13 @@ ap_status run_epoch(ap_problem* h, const ap_state* st, hipStream_t s) {
     hipError_t e = hipStreamEndCapture(h->cap, &g);
     if (r != AP_OK || e != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
-      return r != AP_OK ? r : AP_ERR_HIP;
+      return r != AP_OK ? r : note_hip(e, "hipStreamEndCapture");
     }
     e = hipGraphInstantiate(&h->epoch_exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
       h->epoch_exec = nullptr;
-      return AP_ERR_HIP;
+      return note_hip(e, "hipGraphInstantiate");
     }
     std::memcpy(h->key, key, sizeof(key));
   }
@@ -180,7 +209,10 @@ ap_status ap_factor_blocks(const ap_config* cfg, const float* X, void* ws, size_
     return AP_ERR_UNSUPPORTED;
   if (ws_bytes < L.total) return AP_ERR_WORKSPACE;
   ap_problem* h = new (std::nothrow) ap_problem();
-  if (!h) return AP_ERR_HIP;
+  if (!h) {
+    std::snprintf(g_last_error, sizeof(g_last_error), "host allocation of the handle failed");
+    return AP_ERR_HIP;
+  }
   h->L = L;
   h->D = ap::bind(L, ws);
   h->cfg = *cfg;
@@ -190,25 +222,37 @@ ap_status ap_factor_blocks(const ap_config* cfg, const float* X, void* ws, size_
   for (int k = 0; k < ap::kMaxD; ++k) h->P.ell[k] = k < cfg->d ? cfg->lengthscale[k] : 1.0;
   h->P.s = cfg->outputscale;
   h->P.noise = cfg->noise;
-  if (hipGetDevice(&h->device) != hipSuccess) {
+  clear_foreign_error();
+  hipError_t he = hipGetDevice(&h->device);
+  if (he != hipSuccess) {
     delete h;
-    return AP_ERR_HIP;
+    return note_hip(he, "hipGetDevice");
   }
   for (int i = 0; i < 4; ++i) {
-    if (hipEventCreate(&h->ev[i]) != hipSuccess) {
+    he = hipEventCreate(&h->ev[i]);
+    if (he != hipSuccess) {
       for (int k = 0; k < i; ++k) (void)hipEventDestroy(h->ev[k]);
       delete h;
-      return AP_ERR_HIP;
+      return note_hip(he, "hipEventCreate");
     }
   }
-  ap_status r = AP_OK;
+  h->desc = ap::Desc{};
+  h->desc.L = L;
+  h->desc.D = h->D;
+  h->desc.P = h->P;
+  h->desc.X = X;
+  h->desc.tol = cfg->tol;
+  h->desc.min_epochs = cfg->min_epochs;
+  h->desc.max_epochs = cfg->max_epochs;
+  h->desc.refine_every = cfg->refine_every;
+  h->desc_dev = (ap::Desc*)((char*)ws + L.off_desc);
+  ap_status r = hip_fail(ap::launch_prep(L, h->D, h->P, X, stream));
+  if (r == AP_OK) r = hip_fail(ap::launch_factor(L, h->D, h->P, X, stream));
+  if (r == AP_OK)
+    r = hip_fail(hipMemcpyAsync(h->desc_dev, &h->desc, sizeof(ap::Desc), hipMemcpyHostToDevice,
+                                stream));
   ap::Ctl ctl;
-  if (ap::launch_prep(L, h->D, h->P, X, stream) != hipSuccess ||
-      ap::launch_factor(L, h->D, h->P, X, stream) != hipSuccess) {
-    r = AP_ERR_HIP;
-  } else {
-    r = read_ctl(h, stream, &ctl);
-  }
+  if (r == AP_OK) r = read_ctl(h, stream, &ctl);
   if (r == AP_OK && ctl.fail != ~0ull) {
     if (bad_block) *bad_block = (int64_t)(ctl.fail >> 32);
     r = AP_ERR_NOT_PD;
@@ -223,6 +267,7 @@ ap_status ap_factor_blocks(const ap_config* cfg, const float* X, void* ws, size_
 
 ap_status ap_reset(ap_handle h, const ap_state* st, hipStream_t stream) {
   if (!valid_handle(h) || !valid_state(st)) return AP_ERR_INVALID_ARG;
+  clear_foreign_error();
   return hip_fail(ap::launch_reset(h->L, h->D, st->B, st->W, st->R, stream));
 }
 
@@ -231,6 +276,7 @@ ap_status ap_epoch(const ap_handle* h, const ap_state* st, int32_t count, int32_
   if (!h || !st || count < 1 || epochs < 0) return AP_ERR_INVALID_ARG;
   for (int32_t p = 0; p < count; ++p)
     if (!valid_handle(h[p]) || !valid_state(&st[p])) return AP_ERR_INVALID_ARG;
+  clear_foreign_error();
   for (int32_t e = 0; e < epochs; ++e)
     for (int32_t p = 0; p < count; ++p) {
       ap_status r = run_epoch(h[p], &st[p], stream);
@@ -242,6 +288,7 @@ ap_status ap_epoch(const ap_handle* h, const ap_state* st, int32_t count, int32_
 ap_status ap_update(ap_handle h, const ap_state* st, int32_t block, hipStream_t stream) {
   if (!valid_handle(h) || !valid_state(st)) return AP_ERR_INVALID_ARG;
   if (block < 0 || block >= h->L.m) return AP_ERR_INVALID_ARG;
+  clear_foreign_error();
   return one_update(h, st, block, true, stream);
 }
 
@@ -260,6 +307,7 @@ ap_status ap_rel_residual(ap_handle h, hipStream_t stream, double* rho, double* 
 ap_status ap_residual(ap_handle h, const ap_state* st, float* R_out, double* col_rel,
                       hipStream_t stream) {
   if (!valid_handle(h) || !valid_state(st)) return AP_ERR_INVALID_ARG;
+  clear_foreign_error();
   const bool in_place = R_out == nullptr || R_out == st->R;
   if (in_place) {
     ap_status r = refine(h, st, stream);
@@ -363,6 +411,7 @@ ap_status ap_set_tile(ap_handle h, int32_t tile) {
 
 ap_status ap_block_inverse(ap_handle h, int32_t j, double* dst, hipStream_t stream) {
   if (!valid_handle(h) || !dst || j < 0 || j >= h->L.m) return AP_ERR_INVALID_ARG;
+  clear_foreign_error();
   return hip_fail(ap::launch_copy_inverse(h->L, h->D, j, dst, stream));
 }
 
@@ -389,16 +438,99 @@ ap_status ap_profile_read(ap_handle h, hipStream_t stream, double* seconds, int6
   return AP_OK;
 }
 
+ap_status ap_batch_step(const ap_handle* h, const ap_state* st, int32_t count, int32_t steps,
+                        hipStream_t stream) {
+  if (!h || !st || count < 1 || count > ap::kMaxBatch || steps < 0) return AP_ERR_INVALID_ARG;
+  for (int32_t p = 0; p < count; ++p) {
+    if (!valid_handle(h[p]) || !valid_state(&st[p])) return AP_ERR_INVALID_ARG;
+    for (int32_t q = 0; q < p; ++q)
+      if (h[q] == h[p]) return AP_ERR_INVALID_ARG;
+  }
+  clear_foreign_error();
+  // gp: solve partials, gf: solve finish, ga: advance (all problems);
+  // gs: the fused update of the problems on split tiles
+  ap::Group gp{}, gf{}, ga{}, gs{};
+  int32_t ns = 0;
+  for (int32_t p = 0; p < count; ++p) {
+    const ap::Layout& L = h[p]->L;
+    for (ap::Group* g : {&gp, &gf, &ga}) {
+      g->desc[p] = h[p]->desc_dev;
+      g->R[p] = st[p].R;
+      g->W[p] = st[p].W;
+      g->tile[p] = L.tile;
+    }
+    gp.wg0[p + 1] = gp.wg0[p] + (L.b_pad / 64) * ap::kBsSplit;
+    gf.wg0[p + 1] = gf.wg0[p] + (L.b_pad * ap::kMaxL + 255) / 256;
+    ga.wg0[p + 1] = ga.wg0[p] + 1;
+    if (L.tile == AP_TILE_SPLIT) {
+      gs.desc[ns] = h[p]->desc_dev;
+      gs.R[ns] = st[p].R;
+      gs.W[ns] = st[p].W;
+      gs.tile[ns] = L.tile;
+      gs.wg0[ns + 1] = gs.wg0[ns] + L.nwg;
+      ++ns;
+    }
+  }
+  gp.count = gf.count = ga.count = count;
+  gs.count = ns;
+  for (int32_t s = 0; s < steps; ++s) {
+    AP_HIP(ap::launch_group_solve(gp, gf, stream));
+    if (ns > 0) AP_HIP(ap::launch_group_split(gs, stream));
+    for (int32_t p = 0; p < count; ++p) {
+      ap_problem* q = h[p];
+      const bool greedy = q->L.order == AP_GREEDY;
+      const int code = greedy ? ap::kBlockBatchGreedy : ap::kBlockBatchCyclic;
+      if (q->L.tile == AP_TILE_FP64)
+        AP_HIP(ap::launch_fused_update64(q->L, q->D, q->P, q->X, code, st[p].R, greedy, true,
+                                         stream));
+      else if (q->L.tile != AP_TILE_SPLIT)
+        AP_HIP(ap::launch_fused_update(q->L, q->D, code, st[p].R, greedy, true, stream));
+      if (greedy) AP_HIP(ap::launch_select(q->L, q->D, stream));
+    }
+    AP_HIP(ap::launch_group_advance(ga, stream));
+  }
+  return AP_OK;
+}
+
+ap_status ap_batch_peek(ap_handle h, ap_progress* out) {
+  if (!valid_handle(h) || !out) return AP_ERR_INVALID_ARG;
+  clear_foreign_error();
+  if (!h->peek_stream) AP_HIP(hipStreamCreateWithFlags(&h->peek_stream, hipStreamNonBlocking));
+  if (!h->peek_buf)
+    AP_HIP(hipHostMalloc((void**)&h->peek_buf, sizeof(ap::Ctl), hipHostMallocDefault));
+  AP_HIP(hipMemcpyAsync(h->peek_buf, h->D.ctl, sizeof(ap::Ctl), hipMemcpyDeviceToHost,
+                        h->peek_stream));
+  AP_HIP(hipStreamSynchronize(h->peek_stream));
+  const ap::Ctl& c = *h->peek_buf;
+  out->state = c.state;
+  out->epoch = c.epoch;
+  out->cursor = c.cursor;
+  out->status = c.status;
+  out->rho = c.rho;
+  out->rho_true = c.rho_true;
+  return AP_OK;
+}
+
+ap_status ap_batch_release(ap_handle h, hipStream_t stream) {
+  if (!valid_handle(h)) return AP_ERR_INVALID_ARG;
+  clear_foreign_error();
+  return hip_fail(ap::launch_release(h->D, stream));
+}
+
 void ap_destroy(ap_handle h) {
   if (!h) return;
   drop_graph(h);
   if (h->cap) (void)hipStreamDestroy(h->cap);
+  if (h->peek_stream) (void)hipStreamDestroy(h->peek_stream);
+  if (h->peek_buf) (void)hipHostFree(h->peek_buf);
   for (int i = 0; i < 4; ++i)
     if (h->ev[i]) (void)hipEventDestroy(h->ev[i]);
   for (int p = 0; p < 5; ++p)
     for (hipEvent_t e : h->pool[p]) (void)hipEventDestroy(e);
   delete h;
 }
+
+const char* ap_last_error(void) { return g_last_error; }
 
 const char* ap_status_str(ap_status s) {
   switch (s) {

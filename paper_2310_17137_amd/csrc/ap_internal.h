@@ -33,7 +33,29 @@ struct Ctl {
   double colrel[kMaxL];     // ||R_c|| / ||B_c|| after the last epoch
   double colrel_true[kMaxL];
   double mu[kMaxD];         // feature centre used by the prepared copies
+  // batch steps (ap_batch_step): this problem's progress, kept on the device
+  int32_t cursor;           // updates done in the current epoch
+  int32_t state;            // 0 runs; else why the problem is held (ap_batch_state)
+  int32_t run;              // latched at the end of every batch step from state
+  int32_t pad1;
 };
+
+// Block argument of the solve and update launches: >= 0 names the block;
+// kBlockSel takes the greedy selection in ctl->sel; the batch codes take the
+// problem's own cursor (cyclic) or ctl->sel (greedy) and make the launch a
+// no-op while the problem is held.
+constexpr int kBlockSel = -1;
+constexpr int kBlockBatchCyclic = -2;
+constexpr int kBlockBatchGreedy = -3;
+
+// Block of this launch, or -1 when a batch step skips a held problem (uniform
+// over the workgroup).
+__device__ __forceinline__ int resolve_block(int block, const struct Ctl* ctl) {
+  if (block >= 0) return block;
+  if (block == kBlockSel) return ctl->sel;
+  if (!ctl->run) return -1;
+  return block == kBlockBatchCyclic ? ctl->cursor : ctl->sel;
+}
 
 // Kernel map constants. The prepared features v = (x - mu) / ell * c_feat make
 // the map a function of |v_i - v_j|^2 only:
@@ -52,7 +74,8 @@ struct Layout {
   int32_t nwg;           // workgroups of the fused update: n_pad / kRowsWG
   int32_t nwg_res;       // workgroups of the true residual
   size_t off_ctl, off_xs, off_xrow, off_xcol, off_kinv, off_dinv, off_panel, off_delta,
-      off_bspart, off_dtile, off_rowsq, off_colsq, off_blocknorm, off_respart, off_mupart;
+      off_bspart, off_dtile, off_rowsq, off_colsq, off_blocknorm, off_respart, off_mupart,
+      off_desc;
   size_t total;
 };
 
@@ -79,6 +102,36 @@ struct Params {  // hyperparameters as the kernels need them
   double s, noise;
 };
 
+// Everything a grouped (batch) launch needs to know about one problem, kept in
+// its workspace and written once when its factors are built.
+struct Desc {
+  Layout L;
+  Dev D;
+  Params P;
+  const float* X;
+  double tol;
+  int32_t min_epochs, max_epochs, refine_every, pad;
+};
+
+// Problems of one grouped launch: workgroups [wg0[p], wg0[p+1]) serve problem p.
+constexpr int kMaxBatch = 32;
+struct Group {
+  int32_t count;
+  int32_t wg0[kMaxBatch + 1];
+  const Desc* desc[kMaxBatch];
+  float* R[kMaxBatch];
+  double* W[kMaxBatch];
+  int32_t tile[kMaxBatch];
+};
+
+// Problem of this workgroup in a grouped launch and its workgroup index there.
+__device__ __forceinline__ int group_job(const Group& g, int* local) {
+  int p = 0;
+  while (p + 1 < g.count && (int)blockIdx.x >= g.wg0[p + 1]) ++p;
+  *local = (int)blockIdx.x - g.wg0[p];
+  return p;
+}
+
 bool make_layout(int64_t n, int32_t d, int32_t l, int32_t b, int32_t kernel, int32_t order,
                  int32_t tile, Layout* L);
 Dev bind(const Layout& L, void* ws);
@@ -90,7 +143,7 @@ hipError_t launch_factor(const Layout& L, const Dev& D, const Params& P, const f
                          hipStream_t st);
 hipError_t launch_reset(const Layout& L, const Dev& D, const float* B, double* W, float* R,
                         hipStream_t st);
-// block < 0: read the block index from ctl->sel (greedy order)
+// block: >= 0, kBlockSel or a batch code (see resolve_block)
 hipError_t launch_block_solve(const Layout& L, const Dev& D, const Params& P, int32_t block,
                               const float* R, double* W, hipStream_t st);
 hipError_t launch_fused_update(const Layout& L, const Dev& D, int32_t block, float* R,
@@ -105,5 +158,11 @@ hipError_t launch_residual(const Layout& L, const Dev& D, const Params& P, const
                            hipStream_t st);
 hipError_t launch_copy_inverse(const Layout& L, const Dev& D, int32_t j, double* dst,
                                hipStream_t st);
+
+// ---- grouped launches of a batch step (one launch for many problems) -------
+hipError_t launch_group_solve(const Group& gp, const Group& gf, hipStream_t st);
+hipError_t launch_group_split(const Group& g, hipStream_t st);
+hipError_t launch_group_advance(const Group& g, hipStream_t st);
+hipError_t launch_release(const Dev& D, hipStream_t st);
 
 }  // namespace ap

@@ -53,6 +53,7 @@ bool make_layout(int64_t n, int32_t d, int32_t l, int32_t b, int32_t kernel, int
   o.off_blocknorm = take((size_t)o.m * sizeof(double));
   o.off_respart = take((size_t)std::max(o.nwg_res, 1024) * kMaxL * sizeof(double));
   o.off_mupart = take((size_t)256 * kMaxD * sizeof(double));
+  o.off_desc = take(sizeof(Desc));
   o.total = off;
   *L = o;
   return true;
@@ -128,6 +129,9 @@ __global__ void k_mu_final(Layout L, const double* __restrict__ part, Ctl* ctl) 
     ctl->epoch = 0;
     ctl->rho = 0.0;
     ctl->rho_true = 0.0;
+    ctl->cursor = 0;
+    ctl->state = 0;
+    ctl->run = 1;
   }
 }
 
@@ -264,6 +268,9 @@ __global__ void k_reset_final(Layout L, const double* __restrict__ part, int gro
     ctl->sel = 0;
     ctl->epoch = 0;
     ctl->rho = 1.0;
+    ctl->cursor = 0;
+    ctl->state = 0;
+    ctl->run = 1;
   }
 }
 
@@ -320,8 +327,8 @@ __global__ __launch_bounds__(256) void k_argmax(Layout L, const double* __restri
 // Epoch-end check (Section 5, "Alternating Projection Details"): column norms
 // of R from the fused update's per-workgroup partials, in a fixed order, then
 // rho = mean_c ||r_c|| / ||b_c||.
-__global__ __launch_bounds__(256) void k_epoch_check(Layout L, const float* __restrict__ colsq,
-                                                     Ctl* ctl) {
+__device__ __forceinline__ void epoch_check_body(const Layout& L, const float* __restrict__ colsq,
+                                                 Ctl* ctl) {
   __shared__ double red[256];
   __shared__ double ratio[kMaxL];
   for (int c = 0; c < L.l; ++c) {
@@ -352,6 +359,66 @@ __global__ __launch_bounds__(256) void k_epoch_check(Layout L, const float* __re
   }
 }
 
+__global__ __launch_bounds__(256) void k_epoch_check(Layout L, const float* __restrict__ colsq,
+                                                     Ctl* ctl) {
+  epoch_check_body(L, colsq, ctl);
+}
+
+// Batch step epilogue, one workgroup per problem of the group: a problem that
+// updated in this step advances its cursor; after the last block of an epoch
+// the epoch-end check runs and the problem is held when the host has to act:
+// the ratio is not finite, it is below the tolerance (with at least
+// min_epochs epochs), max_epochs is reached, or an FP64 true residual is due
+// every refine_every epochs. The run flag of the next step is latched here, so
+// a problem is either updated through a whole step or not at all.
+__global__ __launch_bounds__(256) void g_advance(Group g) {
+  int wg;
+  const int p = group_job(g, &wg);
+  const Desc* ds = g.desc[p];
+  Ctl* ctl = ds->D.ctl;
+  const Layout L = ds->L;
+  const int ran = ctl->run;
+  const int cur = ctl->cursor + 1;
+  __syncthreads();  // every thread holds run and cursor before thread 0 rewrites them
+  if (ran) {
+    if (cur == L.m) {
+      epoch_check_body(L, ds->D.colsq, ctl);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const int ep = ctl->epoch;
+        const double rho = ctl->rho;
+        int state = 0;
+        if (ctl->status != 0 || !isfinite(rho))
+          state = 4;
+        else if (rho < ds->tol && ep >= ds->min_epochs)
+          state = 2;
+        else if (ep >= ds->max_epochs)
+          state = 3;
+        else if (ds->refine_every > 0 && ep % ds->refine_every == 0)
+          state = 1;
+        ctl->cursor = 0;
+        ctl->state = state;
+      }
+    } else if (threadIdx.x == 0) {
+      ctl->cursor = cur;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    ctl->run = ctl->state == 0 ? 1 : 0;
+  }
+}
+
+// The host has acted on a held problem: it updates again from the next step.
+__global__ void k_release(Ctl* ctl) {
+  if (threadIdx.x == 0) {
+    ctl->state = 0;
+    ctl->status = 0;
+    ctl->run = 1;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_prep(const Layout& L, const Dev& D, const Params& P, const float* X,
@@ -375,6 +442,16 @@ hipError_t launch_reset(const Layout& L, const Dev& D, const float* B, double* W
 hipError_t launch_select(const Layout& L, const Dev& D, hipStream_t st) {
   hipLaunchKernelGGL(k_block_norms, dim3(L.m), dim3(256), 0, st, L, D.rowsq, D.blocknorm);
   hipLaunchKernelGGL(k_argmax, dim3(1), dim3(256), 0, st, L, D.blocknorm, D.ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_advance(const Group& g, hipStream_t st) {
+  hipLaunchKernelGGL(g_advance, dim3(g.count), dim3(256), 0, st, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_release(const Dev& D, hipStream_t st) {
+  hipLaunchKernelGGL(k_release, dim3(1), dim3(64), 0, st, D.ctl);
   return hipGetLastError();
 }
 

@@ -23,19 +23,22 @@ __device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32
 // interleaved quarters of the slice. The inverse is read along rows of its
 // symmetric storage, K^-1[q][i] = K^-1[i][q], so the 64 lanes of a wave read
 // 512 contiguous bytes per q; R_I is staged once per slice in LDS as FP64.
+constexpr int kSlice = 4096 / kBsSplit;  // largest slice (b_pad <= 4096)
 template <int LB>
-__global__ __launch_bounds__(256) void k_bs_partial(Layout L, const double* __restrict__ kinv,
-                                                    const Ctl* __restrict__ ctl, int block,
-                                                    const float* __restrict__ R,
-                                                    double* __restrict__ part) {
-  constexpr int kSlice = 4096 / kBsSplit;       // largest slice (b_pad <= 4096)
-  __shared__ double smem[kSlice * LB > 4 * 64 * LB ? kSlice * LB : 4 * 64 * LB];
-  const int blk = block >= 0 ? block : ctl->sel;
+constexpr int bs_smem() {
+  return kSlice * LB > 4 * 64 * LB ? kSlice * LB : 4 * 64 * LB;
+}
+
+template <int LB>
+__device__ __forceinline__ void bs_partial_body(const Layout& L, const double* __restrict__ kinv,
+                                                int blk, const float* __restrict__ R,
+                                                double* __restrict__ part, int wg,
+                                                double* smem) {
   const int64_t start = (int64_t)blk * L.b;
   const int len = (int)std::min<int64_t>(L.b, L.n - start);
   const int l = L.l;
   const int ntile = L.b_pad / 64;
-  const int it = blockIdx.x % ntile, sp = blockIdx.x / ntile;
+  const int it = wg % ntile, sp = wg / ntile;
   const int slice = L.b_pad / kBsSplit;  // multiple of 4
   const int q0 = sp * slice;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -70,17 +73,25 @@ __global__ __launch_bounds__(256) void k_bs_partial(Layout L, const double* __re
   }
 }
 
+template <int LB>
+__global__ __launch_bounds__(256) void k_bs_partial(Layout L, const double* __restrict__ kinv,
+                                                    const Ctl* __restrict__ ctl, int block,
+                                                    const float* __restrict__ R,
+                                                    double* __restrict__ part) {
+  __shared__ double smem[bs_smem<LB>()];
+  const int blk = resolve_block(block, ctl);
+  if (blk < 0) return;
+  bs_partial_body<LB>(L, kinv, blk, R, part, (int)blockIdx.x, smem);
+}
+
 // Sum the slices in a fixed order, update W_I, keep delta in FP64 and write
-// s * delta in the fused update's operand layout.
-__global__ __launch_bounds__(256) void k_bs_finish(Layout L, const Ctl* __restrict__ ctl,
-                                                   int block, double s,
-                                                   const double* __restrict__ part,
-                                                   double* __restrict__ W,
-                                                   double* __restrict__ delta, void* dtile) {
-  const int blk = block >= 0 ? block : ctl->sel;
+// s * delta in the fused update's operand layout (element e = i * 32 + c).
+__device__ __forceinline__ void bs_finish_body(const Layout& L, int blk, int tile, double s,
+                                               const double* __restrict__ part,
+                                               double* __restrict__ W,
+                                               double* __restrict__ delta, void* dtile, int e) {
   const int64_t start = (int64_t)blk * L.b;
   const int len = (int)std::min<int64_t>(L.b, L.n - start);
-  const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= L.b_pad * kMaxL) return;
   const int i = e / kMaxL, c = e % kMaxL;
   double v = 0.0;
@@ -89,8 +100,8 @@ __global__ __launch_bounds__(256) void k_bs_finish(Layout L, const Ctl* __restri
     W[(start + i) * L.l + c] += v;
   }
   delta[i * kMaxL + c] = v;
-  if (L.tile == 3) return;  // the FP64-tile update reads delta itself
-  if (L.tile == 0) {
+  if (tile == 3) return;  // the FP64-tile update reads delta itself
+  if (tile == 0) {
     ((float*)dtile)[i * kMaxL + c] = (float)(s * v);
     return;
   }
@@ -101,7 +112,7 @@ __global__ __launch_bounds__(256) void k_bs_finish(Layout L, const Ctl* __restri
   const int lane = g * 32 + c;
   const size_t at = (((size_t)ch * 2 + st) * 64 + lane) * 8 + el;
   uint16_t* out = (uint16_t*)dtile;
-  if (L.tile == 1) {
+  if (tile == 1) {
     out[at] = bf16_rne((float)(s * v));
     return;
   }
@@ -115,6 +126,56 @@ __global__ __launch_bounds__(256) void k_bs_finish(Layout L, const Ctl* __restri
   out[at] = h;
   out[term + at] = m;
   out[2 * term + at] = bf16_rne((float)r2);
+}
+
+__global__ __launch_bounds__(256) void k_bs_finish(Layout L, const Ctl* __restrict__ ctl,
+                                                   int block, double s,
+                                                   const double* __restrict__ part,
+                                                   double* __restrict__ W,
+                                                   double* __restrict__ delta, void* dtile) {
+  const int blk = resolve_block(block, ctl);
+  if (blk < 0) return;
+  bs_finish_body(L, blk, L.tile, s, part, W, delta, dtile, (int)blockIdx.x * 256 + threadIdx.x);
+}
+
+// Grouped forms for a batch step: every workgroup finds its problem in the
+// group and runs the same bodies on that problem's block.
+__device__ __forceinline__ int batch_code(const Layout& L) {
+  return L.order == 1 ? kBlockBatchGreedy : kBlockBatchCyclic;
+}
+
+__global__ __launch_bounds__(256) void g_bs_partial(Group g) {
+  __shared__ double smem[bs_smem<kMaxL>()];
+  int wg;
+  const int p = group_job(g, &wg);
+  const Desc* ds = g.desc[p];
+  const Layout L = ds->L;
+  const int blk = resolve_block(batch_code(L), ds->D.ctl);
+  if (blk < 0) return;
+  const double* kinv = ds->D.kinv;
+  double* part = ds->D.bspart;
+  const float* R = g.R[p];
+  if (L.l <= 1)
+    bs_partial_body<1>(L, kinv, blk, R, part, wg, smem);
+  else if (L.l <= 4)
+    bs_partial_body<4>(L, kinv, blk, R, part, wg, smem);
+  else if (L.l <= 8)
+    bs_partial_body<8>(L, kinv, blk, R, part, wg, smem);
+  else if (L.l <= 16)
+    bs_partial_body<16>(L, kinv, blk, R, part, wg, smem);
+  else
+    bs_partial_body<32>(L, kinv, blk, R, part, wg, smem);
+}
+
+__global__ __launch_bounds__(256) void g_bs_finish(Group g) {
+  int wg;
+  const int p = group_job(g, &wg);
+  const Desc* ds = g.desc[p];
+  const Layout L = ds->L;
+  const int blk = resolve_block(batch_code(L), ds->D.ctl);
+  if (blk < 0) return;
+  bs_finish_body(L, blk, g.tile[p], ds->P.s, ds->D.bspart, g.W[p], ds->D.delta, ds->D.dtile,
+                 wg * 256 + threadIdx.x);
 }
 
 }  // namespace
@@ -136,6 +197,13 @@ hipError_t launch_block_solve(const Layout& L, const Dev& D, const Params& P, in
   const int tot = L.b_pad * kMaxL;
   hipLaunchKernelGGL(k_bs_finish, dim3((tot + 255) / 256), dim3(256), 0, st, L, D.ctl, block,
                      P.s, D.bspart, W, D.delta, D.dtile);
+  return hipGetLastError();
+}
+
+// gp: workgroups (b_pad / 64) kBsSplit per problem; gf: (32 b_pad) / 256.
+hipError_t launch_group_solve(const Group& gp, const Group& gf, hipStream_t st) {
+  hipLaunchKernelGGL(g_bs_partial, dim3(gp.wg0[gp.count]), dim3(256), 0, st, gp);
+  hipLaunchKernelGGL(g_bs_finish, dim3(gf.wg0[gf.count]), dim3(256), 0, st, gf);
   return hipGetLastError();
 }
 

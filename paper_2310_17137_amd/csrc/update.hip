@@ -67,7 +67,7 @@ template <typename Acc>
 __device__ __forceinline__ void epilogue(const Layout& L, int64_t row0, int64_t start, int len,
                                          const Acc acc[2], float* __restrict__ R,
                                          float* __restrict__ rowsq, float* __restrict__ colsq,
-                                         bool want_rowsq, bool want_colsq) {
+                                         bool want_rowsq, bool want_colsq, int wg) {
   __shared__ float red[4][kMaxL];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int nl = lane % 32, g = lane / 32;
@@ -115,7 +115,7 @@ __device__ __forceinline__ void epilogue(const Layout& L, int64_t row0, int64_t 
     if (threadIdx.x < kMaxL) {
       const int m = threadIdx.x;
       float s = ((red[0][m] + red[1][m]) + red[2][m]) + red[3][m];
-      colsq[blockIdx.x * kMaxL + m] = m < l ? s : 0.f;
+      colsq[(size_t)wg * kMaxL + m] = m < l ? s : 0.f;
     }
   }
 }
@@ -130,7 +130,8 @@ __global__ __launch_bounds__(256) void k_fused_bf16(Layout L, const uint16_t* __
                                                     float* __restrict__ rowsq,
                                                     float* __restrict__ colsq, int want_rowsq,
                                                     int want_colsq) {
-  const int blk = block >= 0 ? block : ctl->sel;
+  const int blk = resolve_block(block, ctl);
+  if (blk < 0) return;
   const int64_t start = (int64_t)blk * L.b;
   const int len = (int)std::min<int64_t>(L.b, L.n - start);
   const int nch = (len + kChunk - 1) / kChunk;
@@ -173,7 +174,7 @@ __global__ __launch_bounds__(256) void k_fused_bf16(Layout L, const uint16_t* __
       acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(d1, pack8(s, 8), acc[t], 0, 0, 0);
     }
   }
-  epilogue(L, row0, start, len, acc, R, rowsq, colsq, want_rowsq, want_colsq);
+  epilogue(L, row0, start, len, acc, R, rowsq, colsq, want_rowsq, want_colsq, (int)blockIdx.x);
 }
 
 // FP32 tiles: exact differencing of the prepared (hi, lo) FP32 features, FP32
@@ -187,7 +188,8 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const float* __res
                                                     float* __restrict__ rowsq,
                                                     float* __restrict__ colsq, int want_rowsq,
                                                     int want_colsq) {
-  const int blk = block >= 0 ? block : ctl->sel;
+  const int blk = resolve_block(block, ctl);
+  if (blk < 0) return;
   const int64_t start = (int64_t)blk * L.b;
   const int len = (int)std::min<int64_t>(L.b, L.n - start);
   const int nch = (len + kChunk - 1) / kChunk;
@@ -253,7 +255,7 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const float* __res
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[t][v] += (double)part[t][v];
   }
-  epilogue(L, row0, start, len, acc, R, rowsq, colsq, want_rowsq, want_colsq);
+  epilogue(L, row0, start, len, acc, R, rowsq, colsq, want_rowsq, want_colsq, (int)blockIdx.x);
 }
 
 // Split path: FP32 kernel tiles (exact differencing of FP32 features, FP32
@@ -265,21 +267,17 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const float* __res
 // FP32-grade accuracy at BF16 matrix-core rates. The K operand of each MFMA is
 // built per lane in the BF16 path's column order, so the step layout is shared.
 template <int KERN, int DV, int DP>
-__global__ __launch_bounds__(256) void k_fused_split(Layout L, const float* __restrict__ xs,
-                                                     const uint16_t* __restrict__ dtile,
-                                                     const Ctl* __restrict__ ctl, int block,
-                                                     float* __restrict__ R,
-                                                     float* __restrict__ rowsq,
-                                                     float* __restrict__ colsq, int want_rowsq,
-                                                     int want_colsq) {
-  __shared__ float sx[kChunk][DP];
-  const int blk = block >= 0 ? block : ctl->sel;
+__device__ __forceinline__ void split_body(const Layout& L, const float* __restrict__ xs,
+                                           const uint16_t* __restrict__ dtile, int blk,
+                                           float* __restrict__ R, float* __restrict__ rowsq,
+                                           float* __restrict__ colsq, bool want_rowsq,
+                                           bool want_colsq, int wg, float* sx) {
   const int64_t start = (int64_t)blk * L.b;
   const int len = (int)std::min<int64_t>(L.b, L.n - start);
   const int nch = (len + kChunk - 1) / kChunk;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int nl = lane % 32, g = lane / 32;
-  const int64_t row0 = (int64_t)blockIdx.x * kRowsWG + wave * 64;
+  const int64_t row0 = (int64_t)wg * kRowsWG + wave * 64;
   const size_t term = (size_t)L.b_pad * kMaxL;
 
   float xr[2][DV];
@@ -297,10 +295,7 @@ __global__ __launch_bounds__(256) void k_fused_split(Layout L, const float* __re
   for (int ch = 0; ch < nch; ++ch) {
     const int64_t cb = start + (int64_t)ch * kChunk;
     __syncthreads();
-    for (int e = threadIdx.x; e < kChunk * DP; e += 256) {
-      const int c = e / DP, k = e % DP;
-      sx[c][k] = xs[(cb + c) * DP + k];
-    }
+    for (int e = threadIdx.x; e < kChunk * DP; e += 256) sx[e] = xs[cb * DP + e];
     __syncthreads();
     f32x16 part[2];
 #pragma unroll
@@ -322,7 +317,7 @@ __global__ __launch_bounds__(256) void k_fused_split(Layout L, const float* __re
           float r2 = 0.f;
 #pragma unroll
           for (int k = 0; k < DV; ++k) {
-            const float df = xr[t][k] - sx[cc][k];
+            const float df = xr[t][k] - sx[cc * DP + k];
             r2 = fmaf(df, df, r2);
           }
           kv[e] = kmap_neg<KERN>(-r2);
@@ -347,7 +342,58 @@ __global__ __launch_bounds__(256) void k_fused_split(Layout L, const float* __re
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[t][v] += (double)part[t][v];
   }
-  epilogue(L, row0, start, len, acc, R, rowsq, colsq, want_rowsq, want_colsq);
+  epilogue(L, row0, start, len, acc, R, rowsq, colsq, want_rowsq, want_colsq, wg);
+}
+
+template <int KERN, int DV, int DP>
+__global__ __launch_bounds__(256) void k_fused_split(Layout L, const float* __restrict__ xs,
+                                                     const uint16_t* __restrict__ dtile,
+                                                     const Ctl* __restrict__ ctl, int block,
+                                                     float* __restrict__ R,
+                                                     float* __restrict__ rowsq,
+                                                     float* __restrict__ colsq, int want_rowsq,
+                                                     int want_colsq) {
+  __shared__ float sx[kChunk * DP];
+  const int blk = resolve_block(block, ctl);
+  if (blk < 0) return;
+  split_body<KERN, DV, DP>(L, xs, dtile, blk, R, rowsq, colsq, want_rowsq, want_colsq,
+                           (int)blockIdx.x, sx);
+}
+
+// Grouped split update of a batch step: each workgroup runs the body for its
+// problem's block, with the feature loop over the padded stride (the padded
+// features are zero, so r^2 is the same). Every update writes the column
+// partials; the batch's epoch-end check reads those of the epoch's last one.
+template <int KERN>
+__device__ __forceinline__ void split_dispatch(const Layout& L, const Desc* ds, int blk, float* R,
+                                               int wg, float* sx) {
+  const float* xs = ds->D.xs;
+  const uint16_t* dt = (const uint16_t*)ds->D.dtile;
+  const bool wr = L.order == 1;
+  switch (L.dp) {
+    case 4: split_body<KERN, 4, 4>(L, xs, dt, blk, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx); break;
+    case 8: split_body<KERN, 8, 8>(L, xs, dt, blk, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx); break;
+    case 12: split_body<KERN, 12, 12>(L, xs, dt, blk, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx); break;
+    case 16: split_body<KERN, 16, 16>(L, xs, dt, blk, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx); break;
+    default: split_body<KERN, 20, 20>(L, xs, dt, blk, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx); break;
+  }
+}
+
+__global__ __launch_bounds__(256) void g_fused_split(Group g) {
+  __shared__ float sx[kChunk * kMaxD];
+  int wg;
+  const int p = group_job(g, &wg);
+  const Desc* ds = g.desc[p];
+  const Layout L = ds->L;
+  const int blk =
+      resolve_block(L.order == 1 ? kBlockBatchGreedy : kBlockBatchCyclic, ds->D.ctl);
+  if (blk < 0) return;
+  if (L.kernel == 0)
+    split_dispatch<0>(L, ds, blk, g.R[p], wg, sx);
+  else if (L.kernel == 1)
+    split_dispatch<1>(L, ds, blk, g.R[p], wg, sx);
+  else
+    split_dispatch<2>(L, ds, blk, g.R[p], wg, sx);
 }
 
 template <int KERN>
@@ -402,6 +448,11 @@ hipError_t launch_split(const Layout& L, const Dev& D, int32_t block, float* R, 
 }
 
 }  // namespace
+
+hipError_t launch_group_split(const Group& g, hipStream_t st) {
+  hipLaunchKernelGGL(g_fused_split, dim3(g.wg0[g.count]), dim3(256), 0, st, g);
+  return hipGetLastError();
+}
 
 hipError_t launch_fused_update(const Layout& L, const Dev& D, int32_t block, float* R,
                                bool want_rowsq, bool want_colsq, hipStream_t st) {

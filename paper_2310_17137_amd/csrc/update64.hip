@@ -36,7 +36,8 @@ __global__ __launch_bounds__(256) void k_fused_fp64(Layout L, Params P, const fl
   __shared__ double sx[kCols64][DP];
   __shared__ double sd[kCols64][16 * NH];
   __shared__ float red[4][kMaxL];
-  const int blk = block >= 0 ? block : ctl->sel;
+  const int blk = resolve_block(block, ctl);
+  if (blk < 0) return;
   const int64_t start = (int64_t)blk * L.b;
   const int len = (int)std::min<int64_t>(L.b, L.n - start);
   const int d = L.d, l = L.l;

@@ -32,6 +32,13 @@ def test_library_exports_every_declared_symbol():
         getattr(raw, name)
 
 
+def test_library_shares_torchs_hip_runtime():
+    ap.load()
+    runtimes = ap._hip_runtimes()
+    assert len(runtimes) == 1, runtimes
+    assert ap.last_error() == ""  # nothing failed on this thread
+
+
 def test_status_strings():
     assert ap.status_str(ap.OK) == "ok"
     assert "positive definite" in ap.status_str(ap.ERR_NOT_PD)

@@ -1,0 +1,96 @@
+"""Batch steps (ap_batch_step) on the GPU: a group of problems that differ in n,
+d, l, b, kernel, order and tile mode, advanced together in grouped launches,
+gives bitwise the W and R of each problem run alone with ap_epoch; a held
+problem does not change until it is released; peek reports the device state."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_2310_17137_amd import gen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2310_17137_amd import ap  # noqa: E402
+
+# (seed, n, d, l, b, kernel, noise, ell, order, tile)
+GROUP = [
+    (1, 3000, 3, 5, 512, gen.RBF, 0.05, 0.3, gen.CYCLIC, ap.TILE_SPLIT),
+    (2, 2500, 8, 17, 256, gen.MATERN52, 0.01, 1.0, gen.CYCLIC, ap.TILE_SPLIT),
+    (3, 2000, 3, 3, 512, gen.MATERN32, 0.02, 0.4, gen.CYCLIC, ap.TILE_FP64),
+    (4, 1800, 5, 2, 256, gen.RBF, 0.1, 0.5, gen.GREEDY, ap.TILE_SPLIT),
+    (5, 1100, 16, 32, 200, gen.MATERN32, 0.05, 2.0, gen.CYCLIC, ap.TILE_FP32),
+    (6, 640, 20, 9, 640, gen.MATERN52, 0.1, 2.5, gen.CYCLIC, ap.TILE_SPLIT),  # one block, d = 20
+]
+
+
+def _make(case, **over):
+    seed, n, d, l, b, kern, noise, ell, order, tile = case
+    w = gen.small(seed, n, d, l, b, kernel=kern, noise=noise, ell=ell, order=order)
+    print(f"[batch-case] seed={seed} n={n} d={d} l={l} b={b} kernel={kern} order={order} "
+          f"tile={tile} {over}", flush=True)
+    return ap.from_workload(w, tile=tile, **over)
+
+
+def _steps_to(probs, epochs):
+    return epochs * max(s.m for s, *_ in probs)
+
+
+def test_batch_equals_each_problem_alone():
+    E = 3
+    batch = [_make(c, tol=0.0, max_epochs=E, refine_every=0) for c in GROUP]
+    alone = [_make(c, tol=0.0, max_epochs=E, refine_every=0) for c in GROUP]
+    for s, B, W, R in batch:
+        s.reset(B, W, R)
+    ap.batch_step([p[0] for p in batch], [p[1:] for p in batch], _steps_to(batch, E) + 2)
+    for s, B, W, R in alone:
+        s.reset(B, W, R)
+        s.epoch(B, W, R, E)
+    torch.cuda.synchronize()
+    for c, (sb, _, Wb, Rb), (sa, _, Wa, Ra) in zip(GROUP, batch, alone):
+        pr = sb.peek()
+        rho_a, _ = sa.rel_residual()
+        print(f"[batch] seed {c[0]}: state {pr.state} epoch {pr.epoch} cursor {pr.cursor} "
+              f"rho {pr.rho:.6e} alone {rho_a:.6e}", flush=True)
+        assert pr.state == ap.HOLD_MAX and pr.epoch == E and pr.cursor == 0
+        assert pr.rho == rho_a
+        assert torch.equal(Wb, Wa), c
+        assert torch.equal(Rb, Ra), c
+
+
+def test_held_problem_waits_for_release():
+    case = GROUP[0]
+    s, B, W, R = _make(case, tol=0.0, max_epochs=50, refine_every=2)
+    other = _make(GROUP[1], tol=0.0, max_epochs=50, refine_every=0)
+    probs = [(s, B, W, R), other]
+    for p in probs:
+        p[0].reset(*p[1:])
+    solvers, states = [p[0] for p in probs], [p[1:] for p in probs]
+    ap.batch_step(solvers, states, 2 * s.m + 5)
+    torch.cuda.synchronize()
+    pr = s.peek()
+    assert pr.state == ap.HOLD_REFINE and pr.epoch == 2 and pr.cursor == 0
+    W0, R0 = W.clone(), R.clone()
+    e_other = other[0].peek().epoch
+    ap.batch_step(solvers, states, 3 * other[0].m)
+    torch.cuda.synchronize()
+    assert torch.equal(W, W0) and torch.equal(R, R0)       # held: untouched
+    assert other[0].peek().epoch >= e_other + 2           # the rest of the group ran
+    cols = s.residual(B, W, R)                            # the host's action: refine R
+    assert np.isfinite(cols).all()
+    assert abs(s.peek().rho_true - float(np.mean(cols))) < 1e-12
+    s.release()
+    ap.batch_step(solvers, states, 2 * s.m)
+    torch.cuda.synchronize()
+    pr = s.peek()
+    assert pr.state == ap.HOLD_REFINE and pr.epoch == 4
+    assert not torch.equal(W, W0)
+
+
+def test_batch_rejects_bad_groups():
+    s, B, W, R = _make(GROUP[0])
+    with pytest.raises(ap.ApError):
+        ap.batch_step([s, s], [(B, W, R), (B, W, R)], 1)  # a handle twice
+    with pytest.raises(ap.ApError):
+        ap.batch_step([s], [(B, W, R)], -1)
