@@ -213,7 +213,8 @@ ap_status ap_profile_read(ap_handle h, hipStream_t stream, double* seconds, int6
  * after the last block of an epoch, runs its epoch-end check. The epoch state
  * lives on the device, so the host does not wait between steps. After the
  * check a problem is held (its updates become no-ops) while the host has to act:
- *  AP_HOLD_REFINE     epoch % refine_every == 0 (an FP64 true residual is due),
+ *  AP_HOLD_REFINE     an FP64 true residual is due: epoch % refine_every == 0,
+ *                     or the epoch the last ap_batch_release named,
  *  AP_HOLD_TOL        rho < tol with at least min_epochs epochs,
  *  AP_HOLD_MAX        epoch == max_epochs,
  *  AP_HOLD_NONFINITE  the norms were not finite.
@@ -241,8 +242,12 @@ typedef struct {
 } ap_progress;
 
 /* Enqueue `steps` batch steps of the `count` problems (h[i], st[i]), 1 <= count
- * <= 32, each handle at most once; all on `stream`, asynchronous. Every buffer
- * of every problem must stay allocated until the work completes. */
+ * <= 32, each handle at most once, all on the device of h[0]; asynchronous on
+ * `stream`. Problems on split tiles with d > 8 and problems on other tiles are
+ * updated on a second stream the library keeps per device, forked from and
+ * joined back to `stream` within every step, so batch steps on one device are
+ * issued from one host thread at a time. Every buffer of every problem must
+ * stay allocated until the work completes. */
 ap_status ap_batch_step(const ap_handle* h, const ap_state* st, int32_t count, int32_t steps,
                         hipStream_t stream);
 
@@ -253,8 +258,11 @@ ap_status ap_batch_step(const ap_handle* h, const ap_state* st, int32_t count, i
  * buffer and a stream, freed by ap_destroy. Synchronizes that stream only. */
 ap_status ap_batch_peek(ap_handle h, ap_progress* out);
 
-/* Resume a held problem from the next batch step (stream order). */
-ap_status ap_batch_release(ap_handle h, hipStream_t stream);
+/* Resume a held problem from the next batch step (stream order). next_refine
+ * > 0 moves its next AP_HOLD_REFINE to the end of epoch next_refine (for
+ * instance later when the last true residual showed no drift); 0 keeps the
+ * refine_every schedule. */
+ap_status ap_batch_release(ap_handle h, int32_t next_refine, hipStream_t stream);
 
 /* Free the host-side handle. The caller frees X and the workspace afterwards. */
 void ap_destroy(ap_handle h);

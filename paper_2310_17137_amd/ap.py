@@ -128,7 +128,7 @@ def load():
             "ap_profile_read": (I32, [P, P, D, ctypes.POINTER(I64)]),
             "ap_batch_step": (I32, [ctypes.POINTER(P), S, I32, I32, P]),
             "ap_batch_peek": (I32, [P, ctypes.POINTER(Progress)]),
-            "ap_batch_release": (I32, [P, P]),
+            "ap_batch_release": (I32, [P, I32, P]),
             "ap_destroy": (None, [P]),
             "ap_status_str": (ctypes.c_char_p, [I32]),
             "ap_last_error": (ctypes.c_char_p, []),
@@ -309,8 +309,11 @@ class Solver:
         _check(load().ap_batch_peek(self.handle, ctypes.byref(out)), "ap_batch_peek")
         return out
 
-    def release(self, stream=None):
-        _check(load().ap_batch_release(self.handle, _stream(stream)), "ap_batch_release")
+    def release(self, next_refine: int = 0, stream=None):
+        """Resume a held batch problem; next_refine > 0 sets the epoch of its
+        next true-residual hold (0: the refine_every schedule)."""
+        _check(load().ap_batch_release(self.handle, int(next_refine), _stream(stream)),
+               "ap_batch_release")
 
     def block_inverse(self, j: int, stream=None):
         import torch

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -49,6 +50,17 @@ ap_status note_hip(hipError_t e, const char* where) {
   return AP_ERR_HIP;
 }
 
+// Second stream of batch steps, one per device, created on first use and kept
+// for the life of the process, with the events of its fork from and join to
+// the caller's stream.
+struct Aux {
+  hipStream_t s = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+constexpr int kMaxDevices = 64;
+Aux g_aux[kMaxDevices];
+std::mutex g_aux_mu;
+
 // The launchers check their launches with hipGetLastError, which also returns
 // an error that an earlier HIP call elsewhere in the process left unread. Such
 // an error is not this library's: it is taken off (and kept for ap_last_error)
@@ -68,6 +80,19 @@ void clear_foreign_error() {
     hipError_t e_ = (call);                               \
     if (e_ != hipSuccess) return note_hip(e_, #call);     \
   } while (0)
+
+ap_status aux_stream(int device, Aux** out) {
+  if (device < 0 || device >= kMaxDevices) return AP_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_aux_mu);
+  Aux& a = g_aux[device];
+  if (!a.s) {
+    AP_HIP(hipStreamCreateWithFlags(&a.s, hipStreamNonBlocking));
+    AP_HIP(hipEventCreateWithFlags(&a.fork, hipEventDisableTiming));
+    AP_HIP(hipEventCreateWithFlags(&a.join, hipEventDisableTiming));
+  }
+  *out = &a;
+  return AP_OK;
+}
 
 // Checks every scalar field of the configuration. Returns AP_OK,
 // AP_ERR_INVALID_ARG (out of the method's domain) or AP_ERR_UNSUPPORTED
@@ -447,10 +472,11 @@ ap_status ap_batch_step(const ap_handle* h, const ap_state* st, int32_t count, i
       if (h[q] == h[p]) return AP_ERR_INVALID_ARG;
   }
   clear_foreign_error();
-  // gp: solve partials, gf: solve finish, ga: advance (all problems);
-  // gs: the fused update of the problems on split tiles
-  ap::Group gp{}, gf{}, ga{}, gs{};
-  int32_t ns = 0;
+  // gp: solve partials, gf: solve finish, ga: advance (all problems); gs[0]
+  // and gs[1]: the fused updates of the problems on split tiles with narrow
+  // (d <= 8) and wide features; problems on other tiles get launches of their own
+  ap::Group gp{}, gf{}, ga{}, gs[2]{};
+  int32_t n_other = 0;
   for (int32_t p = 0; p < count; ++p) {
     const ap::Layout& L = h[p]->L;
     for (ap::Group* g : {&gp, &gf, &ga}) {
@@ -463,30 +489,52 @@ ap_status ap_batch_step(const ap_handle* h, const ap_state* st, int32_t count, i
     gf.wg0[p + 1] = gf.wg0[p] + (L.b_pad * ap::kMaxL + 255) / 256;
     ga.wg0[p + 1] = ga.wg0[p] + 1;
     if (L.tile == AP_TILE_SPLIT) {
-      gs.desc[ns] = h[p]->desc_dev;
-      gs.R[ns] = st[p].R;
-      gs.W[ns] = st[p].W;
-      gs.tile[ns] = L.tile;
-      gs.wg0[ns + 1] = gs.wg0[ns] + L.nwg;
-      ++ns;
+      ap::Group& g = gs[L.dp > 8 ? 1 : 0];
+      const int32_t k = g.count++;
+      g.desc[k] = h[p]->desc_dev;
+      g.R[k] = st[p].R;
+      g.W[k] = st[p].W;
+      g.tile[k] = L.tile;
+      g.wg0[k + 1] = g.wg0[k] + L.nwg;
+    } else {
+      ++n_other;
     }
   }
   gp.count = gf.count = ga.count = count;
-  gs.count = ns;
+  // The wide split group and the other tiles run on a second stream beside
+  // the narrow group, between a fork after the solves and a join before the
+  // epoch advance.
+  const bool fork = gs[1].count > 0 || n_other > 0;
+  Aux* aux = nullptr;
+  if (fork) {
+    ap_status r = aux_stream(h[0]->device, &aux);
+    if (r != AP_OK) return r;
+  }
   for (int32_t s = 0; s < steps; ++s) {
     AP_HIP(ap::launch_group_solve(gp, gf, stream));
-    if (ns > 0) AP_HIP(ap::launch_group_split(gs, stream));
-    for (int32_t p = 0; p < count; ++p) {
+    if (fork) {
+      AP_HIP(hipEventRecord(aux->fork, stream));
+      AP_HIP(hipStreamWaitEvent(aux->s, aux->fork, 0));
+    }
+    if (gs[0].count > 0) AP_HIP(ap::launch_group_split(gs[0], false, stream));
+    if (gs[1].count > 0) AP_HIP(ap::launch_group_split(gs[1], true, aux->s));
+    for (int32_t p = 0; p < count && n_other > 0; ++p) {
       ap_problem* q = h[p];
+      if (q->L.tile == AP_TILE_SPLIT) continue;
       const bool greedy = q->L.order == AP_GREEDY;
       const int code = greedy ? ap::kBlockBatchGreedy : ap::kBlockBatchCyclic;
       if (q->L.tile == AP_TILE_FP64)
         AP_HIP(ap::launch_fused_update64(q->L, q->D, q->P, q->X, code, st[p].R, greedy, true,
-                                         stream));
-      else if (q->L.tile != AP_TILE_SPLIT)
-        AP_HIP(ap::launch_fused_update(q->L, q->D, code, st[p].R, greedy, true, stream));
-      if (greedy) AP_HIP(ap::launch_select(q->L, q->D, stream));
+                                         aux->s));
+      else
+        AP_HIP(ap::launch_fused_update(q->L, q->D, code, st[p].R, greedy, true, aux->s));
     }
+    if (fork) {
+      AP_HIP(hipEventRecord(aux->join, aux->s));
+      AP_HIP(hipStreamWaitEvent(stream, aux->join, 0));
+    }
+    for (int32_t p = 0; p < count; ++p)
+      if (h[p]->L.order == AP_GREEDY) AP_HIP(ap::launch_select(h[p]->L, h[p]->D, stream));
     AP_HIP(ap::launch_group_advance(ga, stream));
   }
   return AP_OK;
@@ -511,10 +559,10 @@ ap_status ap_batch_peek(ap_handle h, ap_progress* out) {
   return AP_OK;
 }
 
-ap_status ap_batch_release(ap_handle h, hipStream_t stream) {
-  if (!valid_handle(h)) return AP_ERR_INVALID_ARG;
+ap_status ap_batch_release(ap_handle h, int32_t next_refine, hipStream_t stream) {
+  if (!valid_handle(h) || next_refine < 0) return AP_ERR_INVALID_ARG;
   clear_foreign_error();
-  return hip_fail(ap::launch_release(h->D, stream));
+  return hip_fail(ap::launch_release(h->D, next_refine, stream));
 }
 
 void ap_destroy(ap_handle h) {

@@ -37,7 +37,7 @@ struct Ctl {
   int32_t cursor;           // updates done in the current epoch
   int32_t state;            // 0 runs; else why the problem is held (ap_batch_state)
   int32_t run;              // latched at the end of every batch step from state
-  int32_t pad1;
+  int32_t next_refine;      // > 0: epoch of the next true-residual hold; 0: every refine_every
 };
 
 // Block argument of the solve and update launches: >= 0 names the block;
@@ -161,8 +161,9 @@ hipError_t launch_copy_inverse(const Layout& L, const Dev& D, int32_t j, double*
 
 // ---- grouped launches of a batch step (one launch for many problems) -------
 hipError_t launch_group_solve(const Group& gp, const Group& gf, hipStream_t st);
-hipError_t launch_group_split(const Group& g, hipStream_t st);
+// wide: the group's feature strides are 12 to 20 (else 4 or 8)
+hipError_t launch_group_split(const Group& g, bool wide, hipStream_t st);
 hipError_t launch_group_advance(const Group& g, hipStream_t st);
-hipError_t launch_release(const Dev& D, hipStream_t st);
+hipError_t launch_release(const Dev& D, int32_t next_refine, hipStream_t st);
 
 }  // namespace ap

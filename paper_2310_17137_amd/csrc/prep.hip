@@ -132,6 +132,7 @@ __global__ void k_mu_final(Layout L, const double* __restrict__ part, Ctl* ctl) 
     ctl->cursor = 0;
     ctl->state = 0;
     ctl->run = 1;
+    ctl->next_refine = 0;
   }
 }
 
@@ -271,6 +272,7 @@ __global__ void k_reset_final(Layout L, const double* __restrict__ part, int gro
     ctl->cursor = 0;
     ctl->state = 0;
     ctl->run = 1;
+    ctl->next_refine = 0;
   }
 }
 
@@ -394,7 +396,8 @@ __global__ __launch_bounds__(256) void g_advance(Group g) {
           state = 2;
         else if (ep >= ds->max_epochs)
           state = 3;
-        else if (ds->refine_every > 0 && ep % ds->refine_every == 0)
+        else if (ctl->next_refine > 0 ? ep >= ctl->next_refine
+                                       : ds->refine_every > 0 && ep % ds->refine_every == 0)
           state = 1;
         ctl->cursor = 0;
         ctl->state = state;
@@ -410,12 +413,14 @@ __global__ __launch_bounds__(256) void g_advance(Group g) {
   }
 }
 
-// The host has acted on a held problem: it updates again from the next step.
-__global__ void k_release(Ctl* ctl) {
+// The host has acted on a held problem: it updates again from the next step,
+// with the next true-residual hold at epoch next_refine (0: the schedule).
+__global__ void k_release(Ctl* ctl, int next_refine) {
   if (threadIdx.x == 0) {
     ctl->state = 0;
     ctl->status = 0;
     ctl->run = 1;
+    ctl->next_refine = next_refine;
   }
 }
 
@@ -450,8 +455,8 @@ hipError_t launch_group_advance(const Group& g, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_release(const Dev& D, hipStream_t st) {
-  hipLaunchKernelGGL(k_release, dim3(1), dim3(64), 0, st, D.ctl);
+hipError_t launch_release(const Dev& D, int32_t next_refine, hipStream_t st) {
+  hipLaunchKernelGGL(k_release, dim3(1), dim3(64), 0, st, D.ctl, next_refine);
   return hipGetLastError();
 }
 

@@ -364,23 +364,33 @@ __global__ __launch_bounds__(256) void k_fused_split(Layout L, const float* __re
 // problem's block, with the feature loop over the padded stride (the padded
 // features are zero, so r^2 is the same). Every update writes the column
 // partials; the batch's epoch-end check reads those of the epoch's last one.
-template <int KERN>
+template <int KERN, int WIDE>
 __device__ __forceinline__ void split_dispatch(const Layout& L, const Desc* ds, int blk, float* R,
                                                int wg, float* sx) {
   const float* xs = ds->D.xs;
   const uint16_t* dt = (const uint16_t*)ds->D.dtile;
   const bool wr = L.order == 1;
-  switch (L.dp) {
-    case 4: split_body<KERN, 4, 4>(L, xs, dt, blk, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx); break;
-    case 8: split_body<KERN, 8, 8>(L, xs, dt, blk, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx); break;
-    case 12: split_body<KERN, 12, 12>(L, xs, dt, blk, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx); break;
-    case 16: split_body<KERN, 16, 16>(L, xs, dt, blk, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx); break;
-    default: split_body<KERN, 20, 20>(L, xs, dt, blk, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx); break;
+  if constexpr (WIDE == 0) {
+    if (L.dp == 4)
+      split_body<KERN, 4, 4>(L, xs, dt, blk, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx);
+    else
+      split_body<KERN, 8, 8>(L, xs, dt, blk, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx);
+  } else {
+    if (L.dp == 12)
+      split_body<KERN, 12, 12>(L, xs, dt, blk, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx);
+    else if (L.dp == 16)
+      split_body<KERN, 16, 16>(L, xs, dt, blk, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx);
+    else
+      split_body<KERN, 20, 20>(L, xs, dt, blk, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx);
   }
 }
 
+// WIDE = 0 serves feature strides 4 and 8, WIDE = 1 strides 12 to 20: the
+// narrow kernel keeps two waves per SIMD, which the wide variants' registers
+// would not allow.
+template <int WIDE>
 __global__ __launch_bounds__(256) void g_fused_split(Group g) {
-  __shared__ float sx[kChunk * kMaxD];
+  __shared__ float sx[kChunk * (WIDE ? kMaxD : 8)];
   int wg;
   const int p = group_job(g, &wg);
   const Desc* ds = g.desc[p];
@@ -389,11 +399,11 @@ __global__ __launch_bounds__(256) void g_fused_split(Group g) {
       resolve_block(L.order == 1 ? kBlockBatchGreedy : kBlockBatchCyclic, ds->D.ctl);
   if (blk < 0) return;
   if (L.kernel == 0)
-    split_dispatch<0>(L, ds, blk, g.R[p], wg, sx);
+    split_dispatch<0, WIDE>(L, ds, blk, g.R[p], wg, sx);
   else if (L.kernel == 1)
-    split_dispatch<1>(L, ds, blk, g.R[p], wg, sx);
+    split_dispatch<1, WIDE>(L, ds, blk, g.R[p], wg, sx);
   else
-    split_dispatch<2>(L, ds, blk, g.R[p], wg, sx);
+    split_dispatch<2, WIDE>(L, ds, blk, g.R[p], wg, sx);
 }
 
 template <int KERN>
@@ -449,8 +459,11 @@ hipError_t launch_split(const Layout& L, const Dev& D, int32_t block, float* R, 
 
 }  // namespace
 
-hipError_t launch_group_split(const Group& g, hipStream_t st) {
-  hipLaunchKernelGGL(g_fused_split, dim3(g.wg0[g.count]), dim3(256), 0, st, g);
+hipError_t launch_group_split(const Group& g, bool wide, hipStream_t st) {
+  if (wide)
+    hipLaunchKernelGGL(g_fused_split<1>, dim3(g.wg0[g.count]), dim3(256), 0, st, g);
+  else
+    hipLaunchKernelGGL(g_fused_split<0>, dim3(g.wg0[g.count]), dim3(256), 0, st, g);
   return hipGetLastError();
 }
 

@@ -13,7 +13,8 @@ l and hyperparameters share every launch and the device never waits for the
 host between steps. A request's epoch-end check runs on the device and holds
 the request when the host has to act: every refine_every epochs and when the
 maintained ratio is below the tolerance, the host replaces R by the FP64 true
-residual (Lemma residual_equality) and tests it; the request finishes when that
+residual (Lemma residual_equality) and tests it (the interval doubles, up to
+16 refine_every, while the two ratios agree to 1e-3); the request finishes when that
 ratio is below the tolerance or at max_epochs, moves to FP64 tiles when the
 true and maintained ratios differ by more than 5%, and restarts on FP64 tiles
 if its norms were not finite.
@@ -72,6 +73,7 @@ class _Active:
         self.admitted, self.fp, self.tile = admitted, fp, tile
         self.hold = ap.RUN          # state being handled
         self.refine_event = None    # FP64 true residual in flight
+        self.interval = 0           # epochs between true-residual holds (0: none)
         # release (or reset) in flight: until it has run, the device still
         # shows the old held state, which must not be acted on again
         self.resume_event = None
@@ -117,7 +119,9 @@ class Server:
         adm.synchronize()
         s.reset(B, W, R, stream=main)
         fp = footprint_bytes(w.n, w.d, w.l, w.b, w.kernel, self.tile)
-        return _Active(req, w, s, X, B, W, R, now, fp, self.tile)
+        a = _Active(req, w, s, X, B, W, R, now, fp, self.tile)
+        a.interval = self.refine_every
+        return a
 
     def _on_hold(self, a: _Active, pr, main):
         """`a` was seen held (state pr.state): start the host's action."""
@@ -151,10 +155,20 @@ class Server:
             return True, True, rho_t, pr.epoch
         if a.hold == ap.HOLD_MAX:
             return True, False, rho_t, pr.epoch
-        if a.tile != ap.TILE_FP64 and abs(rho_t - pr.rho) > 0.05 * rho_t:
+        drift = abs(rho_t - pr.rho) / rho_t
+        if a.tile != ap.TILE_FP64 and drift > 0.05:
             a.solver.set_tile(ap.TILE_FP64)
             a.tile = ap.TILE_FP64
-        a.solver.release(stream=main)
+        if a.interval > 0:
+            # the true residual costs about as much as a few epochs: while the
+            # maintained residual shows no drift, check less often
+            if a.hold == ap.HOLD_REFINE:
+                a.interval = (min(2 * a.interval, 16 * self.refine_every) if drift < 1e-3
+                              else self.refine_every)
+            nxt = pr.epoch + a.interval
+        else:
+            nxt = 0
+        a.solver.release(next_refine=nxt, stream=main)
         self._resumed(a, main)
         return False, False, rho_t, pr.epoch
 

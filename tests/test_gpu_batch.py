@@ -86,6 +86,11 @@ def test_held_problem_waits_for_release():
     pr = s.peek()
     assert pr.state == ap.HOLD_REFINE and pr.epoch == 4
     assert not torch.equal(W, W0)
+    s.release(next_refine=7)  # postpone the next hold past the schedule's epoch 6
+    ap.batch_step(solvers, states, 4 * s.m)
+    torch.cuda.synchronize()
+    pr = s.peek()
+    assert pr.state == ap.HOLD_REFINE and pr.epoch == 7
 
 
 def test_batch_rejects_bad_groups():
