@@ -75,8 +75,18 @@ def log(*a):
 
 def workload(name: str):
     from paper_2310_17137_amd import gen
-    if name == "c3":
-        return gen.c3()
+    if name == "c3" or name.startswith("c3-"):
+        # variants of the same inputs: c3-noise<sigma^2>, c3-l<right-hand sides>, or both
+        import re
+        m = re.fullmatch(r"c3(?:-noise([0-9.]+(?:e-?[0-9]+)?))?(?:-l([0-9]+))?", name)
+        if not m:
+            raise SystemExit(f"unknown workload {name}")
+        kw = {}
+        if m.group(1):
+            kw["noise"] = float(m.group(1))
+        if m.group(2):
+            kw["l"] = int(m.group(2))
+        return gen.c3(**kw)
     if name == "c2":
         return gen.c2()
     if name == "c4":
@@ -119,6 +129,54 @@ def cpu_baseline(w, updates: int) -> dict:
             "cpu": platform.processor() or platform.machine()}
 
 
+def time_to_tol(w, make, B, tiles):
+    """ap_solve per tile path; a watcher thread reports the epoch and ratio
+    every 20 s (ap_batch_peek reads the control block while the solve runs)."""
+    import threading
+    from paper_2310_17137_amd import ap
+    by_name = {v: k for k, v in TILE_NAMES.items()}
+    runs = []
+    for name in tiles:
+        s, t_factor = make(by_name[name])
+        W, R = s.new_state(B)
+        box = {}
+
+        def work():
+            try:
+                box["st"] = s.solve(B, W, R)
+            except ap.ApError as e:
+                box["err"] = str(e)
+
+        th = threading.Thread(target=work)
+        t0 = time.perf_counter()
+        th.start()
+        trace = []
+        while th.is_alive():
+            th.join(timeout=20.0)
+            if th.is_alive():
+                pr = s.peek()
+                trace.append((round(time.perf_counter() - t0, 1), pr.epoch, pr.rho))
+                log(f"[tol] {name}: {trace[-1][0]:.0f} s, epoch {pr.epoch}, rho {pr.rho:.5f}")
+        wall = time.perf_counter() - t0
+        run = {"tile": name, "factor_s": t_factor, "wall_s": wall, "trace": trace}
+        if "err" in box:
+            run["error"] = box["err"]
+        else:
+            st = box["st"]
+            run.update({"converged": st.converged, "epochs": st.epochs, "refines": st.refines,
+                        "t_epochs": st.t_epochs, "t_refine": st.t_refine,
+                        "time_to_tol_s": st.t_epochs + st.t_refine if st.converged else None,
+                        "rho_maintained": st.rho_maintained, "rho_true": st.rho_true,
+                        "final_tile": TILE_NAMES[st.tile], "escalated_at": st.escalated_at})
+        log(f"[tol] {name}: {json.dumps(run)}")
+        runs.append(run)
+        del s, W, R
+        import torch
+        torch.cuda.empty_cache()
+    print(json.dumps({"time_to_tol": runs, "workload": describe(w), "tol": w.tol,
+                      "refine_every": w.refine_every, "max_epochs": w.max_epochs}), flush=True)
+
+
 def main():
     ap_ = argparse.ArgumentParser()
     ap_.add_argument("--gpus", type=int, default=1)
@@ -132,6 +190,12 @@ def main():
     ap_.add_argument("--cpu-updates", type=int, default=2)
     ap_.add_argument("--no-cpu", action="store_true")
     ap_.add_argument("--no-true-residual", action="store_true")
+    ap_.add_argument("--time-to-tol", default="",
+                     help="comma-separated tile paths: run ap_solve on each (reset, epochs, "
+                          "FP64 true-residual refinement and confirmation) and print the time "
+                          "to the tolerance instead of the epoch-rate line")
+    ap_.add_argument("--max-epochs", type=int, default=0,
+                     help="with --time-to-tol: epoch limit (0: the workload's)")
     ap_.add_argument("--copy-calibration", action="store_true",
                      help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap_.parse_args()
@@ -171,6 +235,12 @@ def main():
                       max_epochs=w.max_epochs)
         torch.cuda.synchronize()
         return s, time.perf_counter() - t0
+
+    if args.time_to_tol:
+        if args.max_epochs > 0:
+            w.max_epochs = args.max_epochs
+        time_to_tol(w, make, B, args.time_to_tol.split(","))
+        return
 
     def run_path(tile, steps, warmup, want_true):
         """Factor, reset, warm up, time `steps` epochs with per-phase events."""

@@ -31,7 +31,8 @@
  *    ap_factor_blocks, ap_solve, ap_rel_residual and ap_residual with a non-NULL
  *    col_rel synchronize that stream (ap_batch_peek synchronizes a stream of
  *    its own). A handle is used by one host thread at a
- *    time, and calls that overlap on one handle race.
+ *    time, and calls that overlap on one handle race, except ap_batch_peek,
+ *    which only reads and may watch a call running on another thread.
  *  - Errors the device detects (a non-positive pivot, a non-finite residual)
  *    are kept in a status word in the workspace and reported by the next
  *    synchronizing call.
@@ -140,7 +141,8 @@ size_t ap_workspace_bytes(const ap_config* cfg);
  *  out [host] receives the handle on AP_OK.
  *  bad_block [host, may be NULL] receives the first failing block on
  *             AP_ERR_NOT_PD.
- * Synchronizes the stream once. */
+ * The handle also keeps a stream and a small pinned host buffer of its own for
+ * ap_batch_peek. Synchronizes the stream once. */
 ap_status ap_factor_blocks(const ap_config* cfg, const float* X, void* ws, size_t ws_bytes,
                            hipStream_t stream, ap_handle* out, int64_t* bad_block);
 
@@ -171,10 +173,12 @@ ap_status ap_update(ap_handle h, const ap_state* st, int32_t block, hipStream_t 
 ap_status ap_rel_residual(ap_handle h, hipStream_t stream, double* rho, double* col_ratio);
 
 /* Algorithm 1 with the stopping rule: reset, then epochs until rho < tol with
- * at least min_epochs epochs, or max_epochs. Every refine_every epochs, and on
+ * at least min_epochs epochs, or max_epochs. After refine_every epochs, and on
  * a tolerance hit when refine_every > 0 or the tile mode is not FP32, R is
  * replaced by the FP64 true residual (exact by Lemma residual_equality) and the
- * test is repeated on it. If that true residual's ratio and the maintained one
+ * test is repeated on it; the interval between these scheduled true residuals
+ * doubles, up to 16 refine_every, while the true and maintained ratios agree to
+ * 1e-5, and returns to refine_every when they do not. If that true residual's ratio and the maintained one
  * differ by more than 5%, the rest of the solve runs on FP64 tiles from the
  * current W; if an epoch's norms are not finite, the solve restarts from W = 0
  * on FP64 tiles (stats.tile, stats.escalated_at). The handle's own mode is
@@ -252,10 +256,11 @@ ap_status ap_batch_step(const ap_handle* h, const ap_state* st, int32_t count, i
                         hipStream_t stream);
 
 /* Snapshot of a problem's progress, read on a stream of the handle's own (it
- * does not wait for work queued on other streams). The state of a held problem
- * and every value written before it was held are exact; a running problem's
- * fields may be mid-update. The first call allocates a small pinned host
- * buffer and a stream, freed by ap_destroy. Synchronizes that stream only. */
+ * does not wait for work queued on other streams), into a pinned host buffer
+ * the handle keeps. The state of a held problem and every value written before
+ * it was held are exact; a running problem's fields may be mid-update. Also
+ * shows epoch and rho while ap_solve or ap_epoch runs. Synchronizes that stream
+ * only. */
 ap_status ap_batch_peek(ap_handle h, ap_progress* out);
 
 /* Resume a held problem from the next batch step (stream order). next_refine

@@ -253,6 +253,12 @@ ap_status ap_factor_blocks(const ap_config* cfg, const float* X, void* ws, size_
     delete h;
     return note_hip(he, "hipGetDevice");
   }
+  he = hipStreamCreateWithFlags(&h->peek_stream, hipStreamNonBlocking);
+  if (he == hipSuccess) he = hipHostMalloc((void**)&h->peek_buf, sizeof(ap::Ctl), hipHostMallocDefault);
+  if (he != hipSuccess) {
+    ap_destroy(h);
+    return note_hip(he, "peek stream or buffer");
+  }
   for (int i = 0; i < 4; ++i) {
     he = hipEventCreate(&h->ev[i]);
     if (he != hipSuccess) {
@@ -362,6 +368,9 @@ ap_status ap_solve(ap_handle h, const ap_state* st, hipStream_t stream, ap_stats
   ap_status result = AP_NOT_CONVERGED;
   ap::Ctl ctl;
   double t_ep = 0.0, t_ref = 0.0;
+  // epochs between true residuals: doubles (up to 16 refine_every) while the
+  // true and maintained ratios agree to 1e-5, back to refine_every otherwise
+  int32_t interval = c.refine_every, next_ref = c.refine_every;
   for (int32_t t = 1; t <= c.max_epochs; ++t) {
     AP_HIP(hipEventRecord(h->ev[0], stream));
     r = run_epoch(h, st, stream);
@@ -387,7 +396,7 @@ ap_status ap_solve(ap_handle h, const ap_state* st, hipStream_t stream, ap_stats
     t_ep += ms * 1e-3;
     s.epochs = t;
     s.rho_maintained = ctl.rho;
-    const bool scheduled = c.refine_every > 0 && t % c.refine_every == 0;
+    const bool scheduled = c.refine_every > 0 && t >= next_ref;
     const bool hit = ctl.rho < c.tol && t >= c.min_epochs;
     const bool check = scheduled || (hit && (c.refine_every > 0 || h->L.tile != AP_TILE_FP32));
     double rho = ctl.rho;
@@ -408,10 +417,14 @@ ap_status ap_solve(ap_handle h, const ap_state* st, hipStream_t stream, ap_stats
       if (ctl.status != 0 || !std::isfinite(ctl.rho_true)) return AP_ERR_NONFINITE;
       s.rho_true = ctl.rho_true;
       rho = ctl.rho_true;
-      if (h->L.tile != AP_TILE_FP64 &&
-          std::fabs(ctl.rho_true - maintained) > 0.05 * ctl.rho_true) {
+      const double drift = std::fabs(ctl.rho_true - maintained) / ctl.rho_true;
+      if (h->L.tile != AP_TILE_FP64 && drift > 0.05) {
         h->L.tile = AP_TILE_FP64;
         s.escalated_at = t;
+      }
+      if (scheduled) {
+        interval = drift < 1e-5 ? std::min(2 * interval, 16 * c.refine_every) : c.refine_every;
+        next_ref = t + interval;
       }
     }
     if (rho < c.tol && t >= c.min_epochs) {
@@ -542,10 +555,6 @@ ap_status ap_batch_step(const ap_handle* h, const ap_state* st, int32_t count, i
 
 ap_status ap_batch_peek(ap_handle h, ap_progress* out) {
   if (!valid_handle(h) || !out) return AP_ERR_INVALID_ARG;
-  clear_foreign_error();
-  if (!h->peek_stream) AP_HIP(hipStreamCreateWithFlags(&h->peek_stream, hipStreamNonBlocking));
-  if (!h->peek_buf)
-    AP_HIP(hipHostMalloc((void**)&h->peek_buf, sizeof(ap::Ctl), hipHostMallocDefault));
   AP_HIP(hipMemcpyAsync(h->peek_buf, h->D.ctl, sizeof(ap::Ctl), hipMemcpyDeviceToHost,
                         h->peek_stream));
   AP_HIP(hipStreamSynchronize(h->peek_stream));

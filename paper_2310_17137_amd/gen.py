@@ -98,12 +98,14 @@ def c2(seed: int = 0, n: int = 262144, l: int = 16, b: int = 1024) -> Workload:
                     tol=1e-2)
 
 
-def c3(seed: int = 0, n: int = 2_000_000, l: int = 32, b: int = 2048) -> Workload:
+def c3(seed: int = 0, n: int = 2_000_000, l: int = 32, b: int = 2048,
+       noise: float = 1e-4) -> Workload:
     """Ill-conditioned case at house-electric scale: n = 2 000 000, d = 3, a
     64-component Gaussian mixture (centres U[0,1]^3, equal weights, sd 0.02,
     redrawn until inside [0,1]^3), RBF ell = 0.1, s = 1, sigma^2 = 1e-4, b = 2048,
     32 right-hand sides (y = sin(2 pi sum x) + N(0, 0.01^2) and 31 Rademacher),
-    cyclic order, FP64 refinement every 5 epochs, tolerance 1e-2."""
+    cyclic order, FP64 refinement every 5 epochs, tolerance 1e-2. `noise`
+    replaces sigma^2 for the better-conditioned variant of the same inputs."""
     rng = np.random.default_rng(seed)
     d = 3
     centres = rng.uniform(0.0, 1.0, size=(64, d))
@@ -114,7 +116,8 @@ def c3(seed: int = 0, n: int = 2_000_000, l: int = 32, b: int = 2048) -> Workloa
         X[bad] = centres[comp[bad]] + 0.02 * rng.standard_normal((bad.size, d))
         bad = bad[((X[bad] < 0.0) | (X[bad] > 1.0)).any(1)]
     y = np.sin(2 * np.pi * X.sum(1)) + 0.01 * rng.standard_normal(n)
-    return Workload("c3", X.astype(np.float32), _rhs(rng, y, l), RBF, np.full(d, 0.1), 1.0, 1e-4,
+    name = "c3" + ("" if noise == 1e-4 else f"_noise{noise:g}") + ("" if l == 32 else f"_l{l}")
+    return Workload(name, X.astype(np.float32), _rhs(rng, y, l), RBF, np.full(d, 0.1), 1.0, noise,
                     b=b, tol=1e-2, refine_every=5)
 
 

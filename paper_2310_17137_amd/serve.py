@@ -14,7 +14,7 @@ host between steps. A request's epoch-end check runs on the device and holds
 the request when the host has to act: every refine_every epochs and when the
 maintained ratio is below the tolerance, the host replaces R by the FP64 true
 residual (Lemma residual_equality) and tests it (the interval doubles, up to
-16 refine_every, while the two ratios agree to 1e-3); the request finishes when that
+16 refine_every, while the two ratios agree to 1e-5); the request finishes when that
 ratio is below the tolerance or at max_epochs, moves to FP64 tiles when the
 true and maintained ratios differ by more than 5%, and restarts on FP64 tiles
 if its norms were not finite.
@@ -163,7 +163,7 @@ class Server:
             # the true residual costs about as much as a few epochs: while the
             # maintained residual shows no drift, check less often
             if a.hold == ap.HOLD_REFINE:
-                a.interval = (min(2 * a.interval, 16 * self.refine_every) if drift < 1e-3
+                a.interval = (min(2 * a.interval, 16 * self.refine_every) if drift < 1e-5
                               else self.refine_every)
             nxt = pr.epoch + a.interval
         else:
