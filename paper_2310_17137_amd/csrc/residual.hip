@@ -131,6 +131,124 @@ __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const floa
   }
 }
 
+// Few right-hand sides (l <= 8): the product on the vector units (as the FP64
+// fused update does for l <= 8: an FP64 FMA and an FP64 matrix instruction
+// retire multiply-adds at the same rate on gfx950, and the matrix tile would
+// pad l to 16). Each lane accumulates the columns j = 4 st + lane / 16 of its
+// two rows; the four lanes of a row add their partials in a fixed order.
+template <int KERN, int DP, int NV>
+__global__ __launch_bounds__(256) void k_residualv(Layout L, Params P, const float* __restrict__ X,
+                                                   const float* __restrict__ B,
+                                                   const double* __restrict__ W,
+                                                   float* __restrict__ Rout,
+                                                   float* __restrict__ rowsq,
+                                                   double* __restrict__ part) {
+  constexpr int NQ = (NV + 3) / 4;
+  __shared__ double sx[kCols][DP];
+  __shared__ double sw[kCols][NV];
+  __shared__ double red[4][kMaxL];
+  const int d = L.d, l = L.l;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int ln = lane % 16, lg = lane / 16;
+  const int64_t row0 = (int64_t)blockIdx.x * kResWG + wave * 32;
+  double inv_ell[DP], xi[2][DP];
+#pragma unroll
+  for (int k = 0; k < DP; ++k) inv_ell[k] = k < d ? 1.0 / P.ell[k] : 0.0;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int64_t i = row0 + 16 * t + ln;
+#pragma unroll
+    for (int k = 0; k < DP; ++k) xi[t][k] = (i < L.n && k < d) ? (double)X[i * d + k] : 0.0;
+  }
+  double acc[2][NV];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int c = 0; c < NV; ++c) acc[t][c] = 0.0;
+
+  for (int64_t j0 = 0; j0 < L.n; j0 += kCols) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < kCols * DP; e += 256) {
+      const int jj = e / DP, k = e % DP;
+      sx[jj][k] = (j0 + jj < L.n && k < d) ? (double)X[(j0 + jj) * d + k] : 0.0;
+    }
+    for (int e = threadIdx.x; e < kCols * NV; e += 256) {
+      const int jj = e / NV, c = e % NV;
+      sw[jj][c] = (j0 + jj < L.n && c < l) ? W[(j0 + jj) * l + c] : 0.0;
+    }
+    __syncthreads();
+    for (int st = 0; st < kCols / 4; ++st) {
+      const int jj = 4 * st + lg;
+      const int64_t j = j0 + jj;
+      double a[NV];
+#pragma unroll
+      for (int c = 0; c < NV; ++c) a[c] = sw[jj][c];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        double r2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < DP; ++k) {
+          const double df = (xi[t][k] - sx[jj][k]) * inv_ell[k];
+          r2 = fma(df, df, r2);
+        }
+        double kv = kernel_fp64<KERN>(r2, P.s);
+        if (j == row0 + 16 * t + ln) kv += P.noise;
+#pragma unroll
+        for (int c = 0; c < NV; ++c) acc[t][c] = fma(kv, a[c], acc[t][c]);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      acc[t][c] += __shfl_xor(acc[t][c], 16);
+      acc[t][c] += __shfl_xor(acc[t][c], 32);
+    }
+  double csum[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) csum[q] = 0.0;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int64_t i = row0 + 16 * t + ln;
+    const bool live = i < L.n;
+    double rs = 0.0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int c = lg + 4 * q;
+      double v = 0.0;
+#pragma unroll
+      for (int cc = 4 * q; cc < 4 * q + 4 && cc < NV; ++cc)
+        if (cc == c) v = acc[t][cc];
+      if (live && c < l) {
+        const double r = (double)B[i * l + c] - v;
+        Rout[i * l + c] = (float)r;
+        rs = fma(r, r, rs);
+        csum[q] = fma(r, r, csum[q]);
+      }
+    }
+    rs += __shfl_xor(rs, 16);
+    rs += __shfl_xor(rs, 32);
+    if (rowsq && live && lg == 0) rowsq[i] = (float)rs;
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    double x = csum[q];
+    x += __shfl_xor(x, 1);
+    x += __shfl_xor(x, 2);
+    x += __shfl_xor(x, 4);
+    x += __shfl_xor(x, 8);
+    if (ln == 0 && lg + 4 * q < NV) red[wave][lg + 4 * q] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < kMaxL) {
+    const int c = threadIdx.x;
+    double v = 0.0;
+    if (c < NV) v = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+    part[(size_t)blockIdx.x * kMaxL + c] = c < l ? v : 0.0;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_residual_final(Layout L, const double* __restrict__ part,
                                                         Ctl* ctl) {
   __shared__ double red[256];
@@ -174,10 +292,31 @@ void launch_res_d(const Layout& L, const Dev& D, const Params& P, const float* X
   }
 }
 
+template <int KERN, int NV>
+void launch_res_v(const Layout& L, const Params& P, const float* X, const float* B, const double* W,
+                  float* Rout, float* rowsq, double* part, hipStream_t st) {
+  const dim3 g((unsigned)((L.n + kResWG - 1) / kResWG)), t(256);
+  switch (L.dp) {
+    case 4: hipLaunchKernelGGL((k_residualv<KERN, 4, NV>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, part); break;
+    case 8: hipLaunchKernelGGL((k_residualv<KERN, 8, NV>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, part); break;
+    case 12: hipLaunchKernelGGL((k_residualv<KERN, 12, NV>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, part); break;
+    case 16: hipLaunchKernelGGL((k_residualv<KERN, 16, NV>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, part); break;
+    default: hipLaunchKernelGGL((k_residualv<KERN, 20, NV>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, part); break;
+  }
+}
+
 template <int KERN>
 void launch_res_k(const Layout& L, const Dev& D, const Params& P, const float* X, const float* B,
                   const double* W, float* Rout, float* rowsq, hipStream_t st) {
-  if (L.l <= 16)
+  if (L.l <= 1)
+    launch_res_v<KERN, 1>(L, P, X, B, W, Rout, rowsq, D.respart, st);
+  else if (L.l <= 2)
+    launch_res_v<KERN, 2>(L, P, X, B, W, Rout, rowsq, D.respart, st);
+  else if (L.l <= 4)
+    launch_res_v<KERN, 4>(L, P, X, B, W, Rout, rowsq, D.respart, st);
+  else if (L.l <= 8)
+    launch_res_v<KERN, 8>(L, P, X, B, W, Rout, rowsq, D.respart, st);
+  else if (L.l <= 16)
     launch_res_d<KERN, 1>(L, D, P, X, B, W, Rout, rowsq, st);
   else
     launch_res_d<KERN, 2>(L, D, P, X, B, W, Rout, rowsq, st);

@@ -147,6 +147,164 @@ __global__ __launch_bounds__(256) void k_fused_fp64(Layout L, Params P, const fl
   }
 }
 
+// Few right-hand sides (l <= 8): the product with the step on the vector units.
+// On gfx950 a wave's FP64 FMA and an FP64 matrix instruction retire the same
+// number of multiply-adds per cycle on the same pipe, so for l <= 8 the vector
+// form does l multiply-adds per kernel entry where the 16-column matrix tile
+// does 16. A lane accumulates, for each of its four row tiles, the columns
+// j = 4 st + lane / 16 of the block; the four lanes of a row then add their
+// partial sums in a fixed order (every lane ends with the same total).
+template <int KERN, int DV, int DP, int NV>
+__global__ __launch_bounds__(256) void k_fused_fp64v(Layout L, Params P,
+                                                     const float* __restrict__ X,
+                                                     const double* __restrict__ delta,
+                                                     const Ctl* __restrict__ ctl, int block,
+                                                     float* __restrict__ R,
+                                                     float* __restrict__ rowsq,
+                                                     float* __restrict__ colsq, int want_rowsq,
+                                                     int want_colsq) {
+  constexpr int NQ = (NV + 3) / 4;  // output columns per lane
+  __shared__ double sx[kCols64][DP];
+  __shared__ double sd[kCols64][NV];
+  __shared__ float red[4][kMaxL];
+  const int blk = resolve_block(block, ctl);
+  if (blk < 0) return;
+  const int64_t start = (int64_t)blk * L.b;
+  const int len = (int)std::min<int64_t>(L.b, L.n - start);
+  const int d = L.d, l = L.l;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int ln = lane % 16, lg = lane / 16;
+  const int64_t row0 = (int64_t)blockIdx.x * kRowsWG + wave * 64;
+
+  double inv_ell[DV];
+#pragma unroll
+  for (int k = 0; k < DV; ++k) inv_ell[k] = k < d ? 1.0 / P.ell[k] : 0.0;
+  double xi[4][DV];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int64_t i = row0 + 16 * t + ln;
+#pragma unroll
+    for (int k = 0; k < DV; ++k)
+      xi[t][k] = (i < L.n && k < d) ? (double)X[i * d + k] * inv_ell[k] : 0.0;
+  }
+  double acc[4][NV];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int c = 0; c < NV; ++c) acc[t][c] = 0.0;
+
+  for (int c0 = 0; c0 < len; c0 += kCols64) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < kCols64 * DP; e += 256) {
+      const int jj = e / DP, k = e % DP;
+      sx[jj][k] = (c0 + jj < len && k < d) ? (double)X[(start + c0 + jj) * d + k] / P.ell[k] : 0.0;
+    }
+    for (int e = threadIdx.x; e < kCols64 * NV; e += 256) {
+      const int jj = e / NV, c = e % NV;
+      sd[jj][c] = (c0 + jj < len) ? delta[(size_t)(c0 + jj) * kMaxL + c] : 0.0;
+    }
+    __syncthreads();
+    const int steps = std::min(kCols64, len - c0 + 3) / 4;
+    for (int st = 0; st < steps; ++st) {
+      const int jj = 4 * st + lg;
+      double a[NV];
+#pragma unroll
+      for (int c = 0; c < NV; ++c) a[c] = sd[jj][c];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        double r2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < DV; ++k) {
+          const double df = xi[t][k] - sx[jj][k];
+          r2 = fma(df, df, r2);
+        }
+        const double kv = kernel_fp64<KERN>(r2, P.s);
+#pragma unroll
+        for (int c = 0; c < NV; ++c) acc[t][c] = fma(kv, a[c], acc[t][c]);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      acc[t][c] += __shfl_xor(acc[t][c], 16);
+      acc[t][c] += __shfl_xor(acc[t][c], 32);
+    }
+
+  // lane writes columns c = lane / 16 + 4 q of its row
+  float csum[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) csum[q] = 0.f;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int64_t row = row0 + 16 * t + ln;
+    const bool live = row < L.n;
+    const bool in_i = row >= start && row < start + len;
+    float rs = 0.f;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int c = lg + 4 * q;
+      double v = 0.0;
+#pragma unroll
+      for (int cc = 4 * q; cc < 4 * q + 4 && cc < NV; ++cc)
+        if (cc == c) v = acc[t][cc];
+      if (live && c < l) {
+        const float r = in_i ? 0.f : (float)((double)R[row * l + c] - v);
+        R[row * l + c] = r;
+        rs = fmaf(r, r, rs);
+        csum[q] = fmaf(r, r, csum[q]);
+      }
+    }
+    if (want_rowsq) {
+      rs += __shfl_xor(rs, 16);
+      rs += __shfl_xor(rs, 32);
+      if (lg == 0 && row < L.n_pad) rowsq[row] = live ? rs : 0.f;
+    }
+  }
+  if (want_colsq) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      float x = csum[q];
+      x += __shfl_xor(x, 1);
+      x += __shfl_xor(x, 2);
+      x += __shfl_xor(x, 4);
+      x += __shfl_xor(x, 8);
+      if (ln == 0 && lg + 4 * q < NV) red[wave][lg + 4 * q] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxL) {
+      const int c = threadIdx.x;
+      float v = 0.f;
+      if (c < NV) v = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+      colsq[blockIdx.x * kMaxL + c] = c < l ? v : 0.f;
+    }
+  }
+}
+
+template <int KERN, int NV>
+hipError_t launch_nv(const Layout& L, const Dev& D, const Params& P, const float* X, int32_t block,
+                     float* R, bool wr, bool wc, hipStream_t st) {
+  const dim3 g(L.nwg), t(256);
+#define AP_F64V(DV, DP)                                                                          \
+  hipLaunchKernelGGL((k_fused_fp64v<KERN, DV, DP, NV>), g, t, 0, st, L, P, X, D.delta, D.ctl,   \
+                     block, R, D.rowsq, D.colsq, (int)wr, (int)wc)
+  if (L.d == 3) {
+    AP_F64V(3, 4);
+  } else {
+    switch (L.dp) {
+      case 4: AP_F64V(4, 4); break;
+      case 8: AP_F64V(8, 8); break;
+      case 12: AP_F64V(12, 12); break;
+      case 16: AP_F64V(16, 16); break;
+      case 20: AP_F64V(20, 20); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+#undef AP_F64V
+  return hipGetLastError();
+}
+
 template <int KERN, int NH>
 hipError_t launch_nh(const Layout& L, const Dev& D, const Params& P, const float* X, int32_t block,
                      float* R, bool wr, bool wc, hipStream_t st) {
@@ -173,6 +331,10 @@ hipError_t launch_nh(const Layout& L, const Dev& D, const Params& P, const float
 template <int KERN>
 hipError_t launch_k(const Layout& L, const Dev& D, const Params& P, const float* X, int32_t block,
                     float* R, bool wr, bool wc, hipStream_t st) {
+  if (L.l <= 1) return launch_nv<KERN, 1>(L, D, P, X, block, R, wr, wc, st);
+  if (L.l <= 2) return launch_nv<KERN, 2>(L, D, P, X, block, R, wr, wc, st);
+  if (L.l <= 4) return launch_nv<KERN, 4>(L, D, P, X, block, R, wr, wc, st);
+  if (L.l <= 8) return launch_nv<KERN, 8>(L, D, P, X, block, R, wr, wc, st);
   if (L.l <= 16) return launch_nh<KERN, 1>(L, D, P, X, block, R, wr, wc, st);
   return launch_nh<KERN, 2>(L, D, P, X, block, R, wr, wc, st);
 }

@@ -215,12 +215,13 @@ def test_epochs_fp64_tiles_match_oracle(case):
         assert abs(rho - rho_o) <= max(1e-5 * rho_o, 1e-7)
 
 
-def test_c3_generator_fp64_tiles_track_oracle():
+@pytest.mark.parametrize("l", [32, 1])
+def test_c3_generator_fp64_tiles_track_oracle(l):
     """The ill-conditioned n = 2M recipe at n = 32768 (64-cluster mixture, RBF
-    lengthscale 0.1, sigma^2 = 1e-4, b = 2048, 32 right-hand sides): FP64 tiles
-    follow the oracle's iterates over 3 epochs, and the maintained residual
-    stays the true one."""
-    w = gen.c3(n=32768)
+    lengthscale 0.1, sigma^2 = 1e-4, b = 2048, 32 right-hand sides or the target
+    column alone): FP64 tiles follow the oracle's iterates over 3 epochs, and
+    the maintained residual stays the true one."""
+    w = gen.c3(n=32768, l=l)
     s, B, W, R = _gpu(w, tile=ap.TILE_FP64)
     s.reset(B, W, R)
     p = to_oracle(w)
