@@ -31,6 +31,8 @@ __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const floa
   __shared__ double sx[kCols][DP];
   __shared__ double sw[kCols][16 * NH];
   __shared__ double red[4][16 * NH];
+  __shared__ double etab[64];  // s * 2^(j/64) for the exponential
+  scaled_exp_table(etab, P.s);  // visible after the first barrier of the column loop
   const int d = L.d, l = L.l;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int ln = lane % 16, lg = lane / 16;
@@ -75,7 +77,7 @@ __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const floa
           const double df = (xi[t][k] - sx[jj][k]) * inv_ell[k];
           r2 = fma(df, df, r2);
         }
-        double kv = kernel_fp64<KERN>(r2, P.s);
+        double kv = kernel_fp64<KERN>(r2, etab);
         if (j == row0 + 16 * t + ln) kv += P.noise;
 #pragma unroll
         for (int h = 0; h < NH; ++h)
@@ -147,6 +149,8 @@ __global__ __launch_bounds__(256) void k_residualv(Layout L, Params P, const flo
   __shared__ double sx[kCols][DP];
   __shared__ double sw[kCols][NV];
   __shared__ double red[4][kMaxL];
+  __shared__ double etab[64];  // s * 2^(j/64) for the exponential
+  scaled_exp_table(etab, P.s);  // visible after the first barrier of the column loop
   const int d = L.d, l = L.l;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int ln = lane % 16, lg = lane / 16;
@@ -191,7 +195,7 @@ __global__ __launch_bounds__(256) void k_residualv(Layout L, Params P, const flo
           const double df = (xi[t][k] - sx[jj][k]) * inv_ell[k];
           r2 = fma(df, df, r2);
         }
-        double kv = kernel_fp64<KERN>(r2, P.s);
+        double kv = kernel_fp64<KERN>(r2, etab);
         if (j == row0 + 16 * t + ln) kv += P.noise;
 #pragma unroll
         for (int c = 0; c < NV; ++c) acc[t][c] = fma(kv, a[c], acc[t][c]);

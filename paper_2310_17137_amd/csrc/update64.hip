@@ -36,8 +36,10 @@ __global__ __launch_bounds__(256) void k_fused_fp64(Layout L, Params P, const fl
   __shared__ double sx[kCols64][DP];
   __shared__ double sd[kCols64][16 * NH];
   __shared__ float red[4][kMaxL];
+  __shared__ double etab[64];  // s * 2^(j/64) for the exponential
   const int blk = resolve_block(block, ctl);
   if (blk < 0) return;
+  scaled_exp_table(etab, P.s);  // visible after the first barrier of the chunk loop
   const int64_t start = (int64_t)blk * L.b;
   const int len = (int)std::min<int64_t>(L.b, L.n - start);
   const int d = L.d, l = L.l;
@@ -87,7 +89,7 @@ __global__ __launch_bounds__(256) void k_fused_fp64(Layout L, Params P, const fl
           const double df = xi[t][k] - sx[jj][k];
           r2 = fma(df, df, r2);
         }
-        const double kv = kernel_fp64<KERN>(r2, P.s);
+        const double kv = kernel_fp64<KERN>(r2, etab);
 #pragma unroll
         for (int h = 0; h < NH; ++h)
           acc[t][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h], kv, acc[t][h], 0, 0, 0);
@@ -167,8 +169,10 @@ __global__ __launch_bounds__(256) void k_fused_fp64v(Layout L, Params P,
   __shared__ double sx[kCols64][DP];
   __shared__ double sd[kCols64][NV];
   __shared__ float red[4][kMaxL];
+  __shared__ double etab[64];  // s * 2^(j/64) for the exponential
   const int blk = resolve_block(block, ctl);
   if (blk < 0) return;
+  scaled_exp_table(etab, P.s);  // visible after the first barrier of the chunk loop
   const int64_t start = (int64_t)blk * L.b;
   const int len = (int)std::min<int64_t>(L.b, L.n - start);
   const int d = L.d, l = L.l;
@@ -218,7 +222,7 @@ __global__ __launch_bounds__(256) void k_fused_fp64v(Layout L, Params P,
           const double df = xi[t][k] - sx[jj][k];
           r2 = fma(df, df, r2);
         }
-        const double kv = kernel_fp64<KERN>(r2, P.s);
+        const double kv = kernel_fp64<KERN>(r2, etab);
 #pragma unroll
         for (int c = 0; c < NV; ++c) acc[t][c] = fma(kv, a[c], acc[t][c]);
       }
