@@ -368,6 +368,25 @@ void apo_residual_rows(const apo_config* c, const double* X, const double* B, co
   }
 }
 
+/* ---- posterior mean (Section 2, GP regression) ---------------------------- */
+
+/* out[r, :] = sum_j k(xs_r, x_j) W[j, :] for the ns test points xs (ns x d):
+ * with W = K^^{-1} B this is the posterior mean K(X*, X) K^^{-1} B. The noise
+ * term belongs to the training points only, so it does not appear here. */
+void apo_predict(const apo_config* c, const double* X, const double* W, const double* Xs,
+                 int64_t ns, double* out) {
+  int32_t l = c->l, d = c->d;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t r = 0; r < ns; ++r) {
+    double* o = out + r * l;
+    for (int32_t col = 0; col < l; ++col) o[col] = 0.0;
+    for (int64_t j = 0; j < c->n; ++j) {
+      double k = apo_kernel(c, Xs + r * d, X + j * d);
+      for (int32_t col = 0; col < l; ++col) o[col] += k * W[j * l + col];
+    }
+  }
+}
+
 /* B - K^ W over all rows. */
 void apo_residual(const apo_config* c, const double* X, const double* B, const double* W,
                   double* out) {

@@ -57,6 +57,8 @@ void apo_bcd_update(const apo_config* c, const double* X, const double* L, const
                     double* W, int64_t blk);
 void apo_residual_rows(const apo_config* c, const double* X, const double* B, const double* W,
                        const int64_t* rows, int64_t nrows, double* out);
+void apo_predict(const apo_config* c, const double* X, const double* W, const double* Xs,
+                 int64_t ns, double* out);
 void apo_residual(const apo_config* c, const double* X, const double* B, const double* W,
                   double* out);
 

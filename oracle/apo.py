@@ -76,6 +76,7 @@ def _load():
             "apo_bcd_update": (None, [C, P, P, P, P, I64]),
             "apo_residual_rows": (None, [C, P, P, P, P, I64, P]),
             "apo_residual": (None, [C, P, P, P, P]),
+            "apo_predict": (None, [C, P, P, P, I64, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -307,6 +308,16 @@ def residual_rows(p: Problem, W: np.ndarray, rows) -> np.ndarray:
     c = p.cfg()
     _load().apo_residual_rows(ctypes.byref(c), _p(p.X), _p(p.B), _p(W), _p(rows), rows.size,
                               _p(out))
+    return out
+
+
+def predict(p: Problem, W: np.ndarray, Xs: np.ndarray) -> np.ndarray:
+    """Posterior mean K(Xs, X) W at the test points Xs (ns x d), in FP64."""
+    Xs = np.ascontiguousarray(_f64(Xs).reshape(-1, p.d))
+    W = _f64(W)
+    out = np.empty((Xs.shape[0], p.l))
+    c = p.cfg()
+    _load().apo_predict(ctypes.byref(c), _p(p.X), _p(W), _p(Xs), Xs.shape[0], _p(out))
     return out
 
 

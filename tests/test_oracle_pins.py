@@ -370,3 +370,35 @@ def test_single_block_factor_and_update_agree_with_batched():
     apo.update_block(p, apo.factor_one(p, 2), W2, R2, 2)
     np.testing.assert_array_equal(W1, W2)
     np.testing.assert_array_equal(R1, R2)
+
+
+@pytest.mark.parametrize("kernel", [apo.RBF, apo.MATERN32, apo.MATERN52])
+def test_posterior_mean_matches_sklearn_gpr(kernel):
+    """Posterior mean K(X*, X) K^^{-1} y (Section 2): the oracle's predict on
+    the exact weights equals scikit-learn's GaussianProcessRegressor with the
+    same fixed kernel and alpha = sigma^2."""
+    from sklearn.gaussian_process import GaussianProcessRegressor
+    from sklearn.gaussian_process.kernels import ConstantKernel
+    rng = np.random.default_rng(21)
+    ls = np.array([0.3, 0.45, 0.6])
+    X = rng.uniform(size=(400, 3))
+    y = np.sin(6.0 * X.sum(1)) + 0.05 * rng.standard_normal(400)
+    p = apo.Problem(X=X, B=y[:, None].copy(), kernel=kernel, lengthscale=ls, outputscale=1.3,
+                    noise=0.05, b=100)
+    W = np.linalg.solve(dense_khat(p), p.B)
+    Xs = rng.uniform(size=(60, 3))
+    gpr = GaussianProcessRegressor(kernel=ConstantKernel(1.3, "fixed") * sk_kernel(kernel, ls),
+                                   alpha=0.05, optimizer=None).fit(X, y)
+    np.testing.assert_allclose(apo.predict(p, W, Xs)[:, 0], gpr.predict(Xs), rtol=0, atol=1e-10)
+
+
+def test_posterior_mean_at_training_points_closed_form():
+    """At the training points K W* = (K^ - sigma^2 I) W* = B - sigma^2 W* for the
+    exact solution W* = K^^{-1} B (noise enters K^ by index)."""
+    rng = np.random.default_rng(22)
+    X = rng.uniform(size=(300, 2))
+    B = rng.standard_normal((300, 3))
+    p = apo.Problem(X=X, B=B, kernel=apo.MATERN52, lengthscale=np.array([0.2, 0.35]),
+                    outputscale=0.8, noise=0.02, b=64)
+    W = np.linalg.solve(dense_khat(p), B)
+    np.testing.assert_allclose(apo.predict(p, W, X), B - 0.02 * W, rtol=0, atol=1e-10)
