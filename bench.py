@@ -89,6 +89,8 @@ def workload(name: str):
         return gen.c3(**kw)
     if name == "c2":
         return gen.c2()
+    if name.startswith("c2-l") and name[4:].isdigit():
+        return gen.c2(l=int(name[4:]))
     if name == "c4":
         return gen.c4()
     if name == "c1":
@@ -177,6 +179,54 @@ def time_to_tol(w, make, B, tiles):
                       "refine_every": w.refine_every, "max_epochs": w.max_epochs}), flush=True)
 
 
+def bench_predict(w, make, args):
+    """Posterior mean K(X*, X) W at ns test points from the same generator
+    (another seed), W ~ N(0, 1) in FP64 (the rate does not depend on W); the
+    oracle on a few of the points, on this host, beside it."""
+    import torch
+    from paper_2310_17137_amd import ap, gen
+    ns = args.predict if args.predict > 0 else w.n // 4
+    s, t_factor = make(ap.TILE_FP64)
+    rng = np.random.default_rng(5)
+    Wh = rng.standard_normal((w.n, w.l))
+    W = torch.from_numpy(Wh).cuda()
+    if not w.name.startswith("c3"):
+        raise SystemExit("--predict draws its test points from the n = 2M recipe")
+    Xs_h = gen.c3(n=ns, l=1, seed=9).X
+    Xs = torch.from_numpy(np.ascontiguousarray(Xs_h)).cuda()
+    mean = s.predict(W, Xs)  # warm-up
+    torch.cuda.synchronize()
+    reps = max(1, args.steps)
+    t0 = time.perf_counter()
+    for i in range(reps):
+        mean = s.predict(W, Xs)
+        torch.cuda.synchronize()
+        log(f"[predict] call {i + 1} of {reps} done at {time.perf_counter() - t0:.2f} s")
+    dt = (time.perf_counter() - t0) / reps
+    entries = float(ns) * w.n
+    cpu = None
+    if not args.no_cpu:
+        from oracle import apo
+        p = apo.Problem(X=w.X.astype(np.float64), B=w.B.astype(np.float64), kernel=w.kernel,
+                        lengthscale=w.lengthscale, outputscale=w.outputscale, noise=w.noise,
+                        b=w.b)
+        k = 16
+        t1 = time.perf_counter()
+        apo.predict(p, Wh, Xs_h[:k].astype(np.float64))
+        tc = time.perf_counter() - t1
+        cpu = {"value": k / tc, "unit": "predictions/s", "cores": apo.num_threads(),
+               "kind": "oracle", "sample": f"{k} test points in {tc:.1f} s"}
+    out = {"metric": "posterior mean predictions/s", "value": ns / dt, "unit": "predictions/s",
+           "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": dt * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": describe(w), "test_points": ns},
+           "kernel_entries_per_s": entries / dt,
+           "fp64_tflops_2dl": 2.0 * (w.d + w.l) * entries / dt / 1e12,
+           "factor_s": t_factor, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap_ = argparse.ArgumentParser()
     ap_.add_argument("--gpus", type=int, default=1)
@@ -196,6 +246,9 @@ def main():
                           "to the tolerance instead of the epoch-rate line")
     ap_.add_argument("--max-epochs", type=int, default=0,
                      help="with --time-to-tol: epoch limit (0: the workload's)")
+    ap_.add_argument("--predict", type=int, default=-1,
+                     help="time the posterior mean (ap_predict) at this many test points "
+                          "(0: n/4, the paper's 80/20 split) instead of the epoch-rate line")
     ap_.add_argument("--copy-calibration", action="store_true",
                      help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap_.parse_args()
@@ -235,6 +288,10 @@ def main():
                       max_epochs=w.max_epochs)
         torch.cuda.synchronize()
         return s, time.perf_counter() - t0
+
+    if args.predict >= 0:
+        bench_predict(w, make, args)
+        return
 
     if args.time_to_tol:
         if args.max_epochs > 0:

@@ -193,6 +193,17 @@ ap_status ap_solve(ap_handle h, const ap_state* st, hipStream_t stream, ap_stats
 ap_status ap_residual(ap_handle h, const ap_state* st, float* R_out, double* col_rel,
                       hipStream_t stream);
 
+/* Posterior mean at test points (Section 2, GP regression): with weights
+ * W = K^^{-1} B from a solve, mean = K(X*, X) W, the test points' kernel
+ * against the training points (no noise term). FP64 kernel values (exact
+ * differencing, FP64 map) and FP64 products, on the matrix cores for l > 8.
+ *  W    [dev] n x l FP64 (the state's W after ap_solve or epochs).
+ *  Xs   [dev] ns x d FP32 test points (ns >= 0; 0 does nothing).
+ *  mean [dev] ns x l FP64, written.
+ * Asynchronous. */
+ap_status ap_predict(ap_handle h, const double* W, const float* Xs, int64_t ns, double* mean,
+                     hipStream_t stream);
+
 /* Copy the cached inverse of block j, len_j x len_j FP64 row-major, to dst
  * [dev] (len_j = b, or the remainder for the last block). Asynchronous. */
 ap_status ap_block_inverse(ap_handle h, int32_t j, double* dst, hipStream_t stream);

@@ -28,7 +28,7 @@ ERR_WORKSPACE, ERR_HIP, ERR_UNSUPPORTED = -4, -5, -6
 SYMBOLS = ("ap_workspace_bytes", "ap_factor_blocks", "ap_reset", "ap_epoch", "ap_update",
            "ap_rel_residual", "ap_solve", "ap_residual", "ap_block_inverse", "ap_set_tile",
            "ap_profile",
-           "ap_profile_read", "ap_batch_step", "ap_batch_peek", "ap_batch_release",
+           "ap_profile_read", "ap_predict", "ap_batch_step", "ap_batch_peek", "ap_batch_release",
            "ap_destroy", "ap_status_str", "ap_last_error")
 PHASES = ("block_solve", "fused_update", "select", "epoch_check", "true_residual")
 
@@ -123,6 +123,7 @@ def load():
             "ap_solve": (I32, [P, S, P, St]),
             "ap_residual": (I32, [P, S, P, D, P]),
             "ap_block_inverse": (I32, [P, I32, P, P]),
+            "ap_predict": (I32, [P, P, P, I64, P, P]),
             "ap_set_tile": (I32, [P, I32]),
             "ap_profile": (I32, [P, I32]),
             "ap_profile_read": (I32, [P, P, D, ctypes.POINTER(I64)]),
@@ -314,6 +315,22 @@ class Solver:
         next true-residual hold (0: the refine_every schedule)."""
         _check(load().ap_batch_release(self.handle, int(next_refine), _stream(stream)),
                "ap_batch_release")
+
+    def predict(self, W, Xs, stream=None):
+        """Posterior mean K(Xs, X) W (ns x l FP64) at test points Xs (ns x d
+        float32 CUDA tensor)."""
+        import torch
+        if not (Xs.is_cuda and Xs.dtype == torch.float32 and Xs.dim() == 2
+                and Xs.shape[1] == self.d and Xs.is_contiguous()):
+            raise ValueError("Xs must be a contiguous ns x d float32 CUDA tensor")
+        if not (W.is_cuda and W.dtype == torch.float64 and W.shape == (self.n, self.l)):
+            raise ValueError("W must be the n x l float64 weights")
+        ns = int(Xs.shape[0])
+        out = torch.empty((ns, self.l), dtype=torch.float64, device=Xs.device)
+        _check(load().ap_predict(self.handle, ctypes.c_void_p(W.data_ptr()),
+                                 ctypes.c_void_p(Xs.data_ptr()), ns,
+                                 ctypes.c_void_p(out.data_ptr()), _stream(stream)), "ap_predict")
+        return out
 
     def block_inverse(self, j: int, stream=None):
         import torch

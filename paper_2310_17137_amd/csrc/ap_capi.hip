@@ -447,6 +447,14 @@ ap_status ap_set_tile(ap_handle h, int32_t tile) {
   return AP_OK;
 }
 
+ap_status ap_predict(ap_handle h, const double* W, const float* Xs, int64_t ns, double* mean,
+                     hipStream_t stream) {
+  if (!valid_handle(h) || ns < 0 || (ns > 0 && (!W || !Xs || !mean))) return AP_ERR_INVALID_ARG;
+  if (ns >= (int64_t(1) << 31)) return AP_ERR_UNSUPPORTED;
+  clear_foreign_error();
+  return hip_fail(ap::launch_predict(h->L, h->P, h->X, W, Xs, ns, mean, stream));
+}
+
 ap_status ap_block_inverse(ap_handle h, int32_t j, double* dst, hipStream_t stream) {
   if (!valid_handle(h) || !dst || j < 0 || j >= h->L.m) return AP_ERR_INVALID_ARG;
   clear_foreign_error();

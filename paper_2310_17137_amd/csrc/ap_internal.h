@@ -158,6 +158,9 @@ hipError_t launch_residual(const Layout& L, const Dev& D, const Params& P, const
                            hipStream_t st);
 hipError_t launch_copy_inverse(const Layout& L, const Dev& D, int32_t j, double* dst,
                                hipStream_t st);
+// mean (ns x l, FP64) = K(Xs, X) W for ns test points Xs (ns x d, FP32)
+hipError_t launch_predict(const Layout& L, const Params& P, const float* X, const double* W,
+                          const float* Xs, int64_t ns, double* mean, hipStream_t st);
 
 // ---- grouped launches of a batch step (one launch for many problems) -------
 hipError_t launch_group_solve(const Group& gp, const Group& gf, hipStream_t st);

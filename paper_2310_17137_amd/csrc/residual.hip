@@ -21,11 +21,17 @@ typedef __attribute__((ext_vector_type(4))) double f64x4;
 // columns a lane evaluates one kernel entry per row tile (row lane % 16, column
 // lane / 16) in FP64 on the vector ALUs, and the matrix cores accumulate
 // acc[c][i] += W^T[c][j] K^T[j][i] for 16 right-hand sides per half (NH halves).
-template <int KERN, int DP, int NH>
+//
+// With PRED the rows are nr test points Xr instead of the training points: the
+// kernel computes the posterior mean K(Xr, X) W (no noise term, Section 2 GP
+// regression) into mean (nr x l, FP64) and skips the norms.
+template <int KERN, int DP, int NH, bool PRED>
 __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const float* __restrict__ X,
+                                                  const float* __restrict__ Xr, int64_t nr,
                                                   const float* __restrict__ B,
                                                   const double* __restrict__ W,
                                                   float* __restrict__ Rout,
+                                                  double* __restrict__ mean,
                                                   float* __restrict__ rowsq,
                                                   double* __restrict__ part) {
   __shared__ double sx[kCols][DP];
@@ -44,7 +50,7 @@ __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const floa
   for (int t = 0; t < 2; ++t) {
     const int64_t i = row0 + 16 * t + ln;
 #pragma unroll
-    for (int k = 0; k < DP; ++k) xi[t][k] = (i < L.n && k < d) ? (double)X[i * d + k] : 0.0;
+    for (int k = 0; k < DP; ++k) xi[t][k] = (i < nr && k < d) ? (double)Xr[i * d + k] : 0.0;
   }
   f64x4 acc[2][NH];
 #pragma unroll
@@ -78,7 +84,7 @@ __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const floa
           r2 = fma(df, df, r2);
         }
         double kv = kernel_fp64<KERN>(r2, etab);
-        if (j == row0 + 16 * t + ln) kv += P.noise;
+        if (!PRED && j == row0 + 16 * t + ln) kv += P.noise;
 #pragma unroll
         for (int h = 0; h < NH; ++h)
           acc[t][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h], kv, acc[t][h], 0, 0, 0);
@@ -87,6 +93,20 @@ __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const floa
   }
   // lane holds acc[t][h][q] for row row0 + 16 t + lane % 16 and right-hand side
   // c = 16 h + lane / 16 + 4 q (the FP64 16x16 accumulator layout)
+  if constexpr (PRED) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int64_t i = row0 + 16 * t + ln;
+#pragma unroll
+      for (int h = 0; h < NH; ++h)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int c = 16 * h + lg + 4 * q;
+          if (i < nr && c < l) mean[i * l + c] = acc[t][h][q];
+        }
+    }
+    return;
+  }
   double csum[NH][4];
 #pragma unroll
   for (int h = 0; h < NH; ++h)
@@ -95,7 +115,7 @@ __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const floa
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const int64_t i = row0 + 16 * t + ln;
-    const bool live = i < L.n;
+    const bool live = i < nr;
     double rs = 0.0;
 #pragma unroll
     for (int h = 0; h < NH; ++h)
@@ -138,11 +158,13 @@ __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const floa
 // retire multiply-adds at the same rate on gfx950, and the matrix tile would
 // pad l to 16). Each lane accumulates the columns j = 4 st + lane / 16 of its
 // two rows; the four lanes of a row add their partials in a fixed order.
-template <int KERN, int DP, int NV>
+template <int KERN, int DP, int NV, bool PRED>
 __global__ __launch_bounds__(256) void k_residualv(Layout L, Params P, const float* __restrict__ X,
+                                                   const float* __restrict__ Xr, int64_t nr,
                                                    const float* __restrict__ B,
                                                    const double* __restrict__ W,
                                                    float* __restrict__ Rout,
+                                                   double* __restrict__ mean,
                                                    float* __restrict__ rowsq,
                                                    double* __restrict__ part) {
   constexpr int NQ = (NV + 3) / 4;
@@ -162,7 +184,7 @@ __global__ __launch_bounds__(256) void k_residualv(Layout L, Params P, const flo
   for (int t = 0; t < 2; ++t) {
     const int64_t i = row0 + 16 * t + ln;
 #pragma unroll
-    for (int k = 0; k < DP; ++k) xi[t][k] = (i < L.n && k < d) ? (double)X[i * d + k] : 0.0;
+    for (int k = 0; k < DP; ++k) xi[t][k] = (i < nr && k < d) ? (double)Xr[i * d + k] : 0.0;
   }
   double acc[2][NV];
 #pragma unroll
@@ -196,7 +218,7 @@ __global__ __launch_bounds__(256) void k_residualv(Layout L, Params P, const flo
           r2 = fma(df, df, r2);
         }
         double kv = kernel_fp64<KERN>(r2, etab);
-        if (j == row0 + 16 * t + ln) kv += P.noise;
+        if (!PRED && j == row0 + 16 * t + ln) kv += P.noise;
 #pragma unroll
         for (int c = 0; c < NV; ++c) acc[t][c] = fma(kv, a[c], acc[t][c]);
       }
@@ -209,13 +231,29 @@ __global__ __launch_bounds__(256) void k_residualv(Layout L, Params P, const flo
       acc[t][c] += __shfl_xor(acc[t][c], 16);
       acc[t][c] += __shfl_xor(acc[t][c], 32);
     }
+  if constexpr (PRED) {
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      const int64_t i = row0 + 16 * t + ln;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int c = lg + 4 * q;
+        double v = 0.0;
+#pragma unroll
+        for (int cc = 4 * q; cc < 4 * q + 4 && cc < NV; ++cc)
+          if (cc == c) v = acc[t][cc];
+        if (i < nr && c < l) mean[i * l + c] = v;
+      }
+    }
+    return;
+  }
   double csum[NQ];
 #pragma unroll
   for (int q = 0; q < NQ; ++q) csum[q] = 0.0;
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const int64_t i = row0 + 16 * t + ln;
-    const bool live = i < L.n;
+    const bool live = i < nr;
     double rs = 0.0;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -283,47 +321,75 @@ __global__ __launch_bounds__(256) void k_residual_final(Layout L, const double* 
   }
 }
 
-template <int KERN, int NH>
-void launch_res_d(const Layout& L, const Dev& D, const Params& P, const float* X, const float* B,
-                  const double* W, float* Rout, float* rowsq, hipStream_t st) {
-  const dim3 g((unsigned)((L.n + kResWG - 1) / kResWG)), t(256);
+// Rows: nr points Xr (the training points for the residual, test points for
+// the posterior mean); 128 rows per workgroup.
+struct ResArgs {
+  const float* X;
+  const float* Xr;
+  int64_t nr;
+  const float* B;
+  const double* W;
+  float* Rout;
+  double* mean;
+  float* rowsq;
+  double* part;
+};
+
+template <int KERN, int NH, bool PRED>
+void launch_res_d(const Layout& L, const Params& P, const ResArgs& a, hipStream_t st) {
+  const dim3 g((unsigned)((a.nr + kResWG - 1) / kResWG)), t(256);
+#define AP_RES(DP)                                                                           \
+  hipLaunchKernelGGL((k_residual<KERN, DP, NH, PRED>), g, t, 0, st, L, P, a.X, a.Xr, a.nr, a.B, \
+                     a.W, a.Rout, a.mean, a.rowsq, a.part)
   switch (L.dp) {
-    case 4: hipLaunchKernelGGL((k_residual<KERN, 4, NH>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, D.respart); break;
-    case 8: hipLaunchKernelGGL((k_residual<KERN, 8, NH>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, D.respart); break;
-    case 12: hipLaunchKernelGGL((k_residual<KERN, 12, NH>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, D.respart); break;
-    case 16: hipLaunchKernelGGL((k_residual<KERN, 16, NH>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, D.respart); break;
-    default: hipLaunchKernelGGL((k_residual<KERN, 20, NH>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, D.respart); break;
+    case 4: AP_RES(4); break;
+    case 8: AP_RES(8); break;
+    case 12: AP_RES(12); break;
+    case 16: AP_RES(16); break;
+    default: AP_RES(20); break;
   }
+#undef AP_RES
 }
 
-template <int KERN, int NV>
-void launch_res_v(const Layout& L, const Params& P, const float* X, const float* B, const double* W,
-                  float* Rout, float* rowsq, double* part, hipStream_t st) {
-  const dim3 g((unsigned)((L.n + kResWG - 1) / kResWG)), t(256);
+template <int KERN, int NV, bool PRED>
+void launch_res_v(const Layout& L, const Params& P, const ResArgs& a, hipStream_t st) {
+  const dim3 g((unsigned)((a.nr + kResWG - 1) / kResWG)), t(256);
+#define AP_RESV(DP)                                                                          \
+  hipLaunchKernelGGL((k_residualv<KERN, DP, NV, PRED>), g, t, 0, st, L, P, a.X, a.Xr, a.nr, a.B, \
+                     a.W, a.Rout, a.mean, a.rowsq, a.part)
   switch (L.dp) {
-    case 4: hipLaunchKernelGGL((k_residualv<KERN, 4, NV>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, part); break;
-    case 8: hipLaunchKernelGGL((k_residualv<KERN, 8, NV>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, part); break;
-    case 12: hipLaunchKernelGGL((k_residualv<KERN, 12, NV>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, part); break;
-    case 16: hipLaunchKernelGGL((k_residualv<KERN, 16, NV>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, part); break;
-    default: hipLaunchKernelGGL((k_residualv<KERN, 20, NV>), g, t, 0, st, L, P, X, B, W, Rout, rowsq, part); break;
+    case 4: AP_RESV(4); break;
+    case 8: AP_RESV(8); break;
+    case 12: AP_RESV(12); break;
+    case 16: AP_RESV(16); break;
+    default: AP_RESV(20); break;
   }
+#undef AP_RESV
 }
 
-template <int KERN>
-void launch_res_k(const Layout& L, const Dev& D, const Params& P, const float* X, const float* B,
-                  const double* W, float* Rout, float* rowsq, hipStream_t st) {
+template <int KERN, bool PRED>
+void launch_res_k(const Layout& L, const Params& P, const ResArgs& a, hipStream_t st) {
   if (L.l <= 1)
-    launch_res_v<KERN, 1>(L, P, X, B, W, Rout, rowsq, D.respart, st);
+    launch_res_v<KERN, 1, PRED>(L, P, a, st);
   else if (L.l <= 2)
-    launch_res_v<KERN, 2>(L, P, X, B, W, Rout, rowsq, D.respart, st);
+    launch_res_v<KERN, 2, PRED>(L, P, a, st);
   else if (L.l <= 4)
-    launch_res_v<KERN, 4>(L, P, X, B, W, Rout, rowsq, D.respart, st);
+    launch_res_v<KERN, 4, PRED>(L, P, a, st);
   else if (L.l <= 8)
-    launch_res_v<KERN, 8>(L, P, X, B, W, Rout, rowsq, D.respart, st);
+    launch_res_v<KERN, 8, PRED>(L, P, a, st);
   else if (L.l <= 16)
-    launch_res_d<KERN, 1>(L, D, P, X, B, W, Rout, rowsq, st);
+    launch_res_d<KERN, 1, PRED>(L, P, a, st);
   else
-    launch_res_d<KERN, 2>(L, D, P, X, B, W, Rout, rowsq, st);
+    launch_res_d<KERN, 2, PRED>(L, P, a, st);
+}
+
+template <bool PRED>
+void launch_res(const Layout& L, const Params& P, const ResArgs& a, hipStream_t st) {
+  switch (L.kernel) {
+    case 0: launch_res_k<0, PRED>(L, P, a, st); break;
+    case 1: launch_res_k<1, PRED>(L, P, a, st); break;
+    default: launch_res_k<2, PRED>(L, P, a, st); break;
+  }
 }
 
 }  // namespace
@@ -332,13 +398,17 @@ hipError_t launch_residual(const Layout& L, const Dev& D, const Params& P, const
                            const float* B, const double* W, float* Rout, bool in_place,
                            hipStream_t st) {
   // refining in place keeps the greedy rule's row norms in step with R
-  float* rowsq = in_place ? D.rowsq : nullptr;
-  switch (L.kernel) {
-    case 0: launch_res_k<0>(L, D, P, X, B, W, Rout, rowsq, st); break;
-    case 1: launch_res_k<1>(L, D, P, X, B, W, Rout, rowsq, st); break;
-    default: launch_res_k<2>(L, D, P, X, B, W, Rout, rowsq, st); break;
-  }
+  const ResArgs a{X, X, L.n, B, W, Rout, nullptr, in_place ? D.rowsq : nullptr, D.respart};
+  launch_res<false>(L, P, a, st);
   hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(256), 0, st, L, D.respart, D.ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_predict(const Layout& L, const Params& P, const float* X, const double* W,
+                          const float* Xs, int64_t ns, double* mean, hipStream_t st) {
+  if (ns == 0) return hipSuccess;
+  const ResArgs a{X, Xs, ns, nullptr, W, nullptr, mean, nullptr, nullptr};
+  launch_res<true>(L, P, a, st);
   return hipGetLastError();
 }
 

@@ -94,8 +94,8 @@ def c2(seed: int = 0, n: int = 262144, l: int = 16, b: int = 1024) -> Workload:
     X = rng.standard_normal((n, d))
     ell = np.exp(0.5 * rng.standard_normal(d))
     y = np.sin(2 * np.pi * X.sum(1) / d) + 0.1 * rng.standard_normal(n)
-    return Workload("c2", X.astype(np.float32), _rhs(rng, y, l), MATERN52, ell, 1.0, 1e-2, b=b,
-                    tol=1e-2)
+    return Workload("c2" if l == 16 else f"c2_l{l}", X.astype(np.float32), _rhs(rng, y, l),
+                    MATERN52, ell, 1.0, 1e-2, b=b, tol=1e-2)
 
 
 def c3(seed: int = 0, n: int = 2_000_000, l: int = 32, b: int = 2048,

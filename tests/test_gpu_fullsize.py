@@ -1,0 +1,116 @@
+"""Parity at the full workload sizes, in the launch configuration bench.py
+times, on outputs the oracle computes one by one.
+
+Three block updates from Algorithm 1's start (block 0, a middle block and the
+ragged last block; or the greedy rule's choices) on the n = 2 000 000 workload
+with FP64 tiles and on the n = 4 000 000 workload with split tiles and greedy
+selection. For each update the GPU's residual before it (FP32, as stored) is
+the common input, and the oracle gives, in FP64:
+  - the greedy choice: argmax of the block norms (several blocks are a valid
+    answer when their norms tie within the FP32 row-norm rounding);
+  - the step K^_II^{-1} R_I (Cholesky of the block, forward and back
+    substitution), compared with the GPU's change of W_I;
+  - the new residual R_i - K^_{i,I} step on sampled rows (and the ragged
+    tail), compared element by element.
+Bounds: FP32 storage of R (2^-24 |R|), the step's relative difference (the
+GPU multiplies by the explicit FP64 inverse) times sum_q |K_iq||step_q|, and
+for split tiles the FP32 kernel values' rounding, u32 (4 + 4 |ln(k/s)|) per
+term (the argument of exp carries its own rounding times |ln(k/s)|)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import apo
+from paper_2310_17137_amd import gen
+from tests.helpers import to_oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2310_17137_amd import ap  # noqa: E402
+
+U32 = 2.0 ** -24
+
+
+def _rows(n, blk_rows, rng, count=512):
+    tail = np.arange(max(0, n - 40), n)
+    pick = rng.choice(n, size=count, replace=False)
+    return np.unique(np.concatenate([pick, tail, blk_rows[:16], blk_rows[-16:]]))
+
+
+def _check_update(p, w, R0, W0, R1, W1, blk, rows, tile):
+    sl = p.block(blk)
+    Lj = apo.factor_one(p, blk)
+    step = apo.block_solve(Lj, R0[sl].astype(np.float64))
+    got = W1[sl] - W0[sl]
+    e_step = float(np.linalg.norm(got - step) / np.linalg.norm(step))
+    untouched = np.ones(p.n, dtype=bool)
+    untouched[sl] = False
+    assert np.array_equal(W1[untouched], W0[untouched])
+    K = np.concatenate([apo.khat_block(p, slice(int(i), int(i) + 1), sl) for i in rows])
+    ref = R0[rows].astype(np.float64) - K @ step
+    inb = (rows >= sl.start) & (rows < sl.stop)
+    ref[inb] = 0.0
+    absk = np.abs(K)
+    mag = absk @ np.abs(step)
+    tol = U32 * np.abs(ref) + 2.0 * max(e_step, 1e-12) * mag
+    if tile != ap.TILE_FP64:
+        kn = absk.copy()
+        kn[rows[:, None] == np.arange(sl.start, sl.stop)[None, :]] -= p.noise
+        cond = np.abs(np.log(np.maximum(kn / p.outputscale, 1e-300)))
+        tol += U32 * (4.0 * np.abs(R0[rows]) + ((4.0 + 4.0 * cond) * absk) @ np.abs(step))
+    err = np.abs(R1[rows].astype(np.float64) - ref)
+    worst = float(np.max(err / np.maximum(tol, 1e-300)))
+    amp = float(np.linalg.norm(mag) / max(np.linalg.norm(ref), 1e-300))
+    print(f"[fullsize] {w.name} block {blk}: step rel diff {e_step:.2e}, worst err/bound "
+          f"{worst:.3f}, amplification {amp:.2e}", flush=True)
+    assert e_step < 1e-6
+    assert np.all(err <= tol)
+    assert np.all(R1[rows][inb] == 0.0)
+
+
+def _run(w, tile, blocks=None):
+    print(f"[fullsize-case] {w.name} n={w.n} d={w.d} l={w.l} b={w.b} tile={tile} "
+          f"order={w.order}", flush=True)
+    s, B, W, R = ap.from_workload(w, tile=tile, tol=0.0, refine_every=0)
+    s.reset(B, W, R)
+    torch.cuda.synchronize()
+    p = to_oracle(w)
+    rng = np.random.default_rng(1)
+    greedy = w.order == gen.GREEDY
+    for k in range(3):
+        R0, W0 = R.cpu().numpy(), W.cpu().numpy()
+        if greedy:
+            ap.batch_step([s], [(B, W, R)], 1)  # one update on the selected block
+        else:
+            s.update(B, W, R, blocks[k])
+        torch.cuda.synchronize()
+        R1, W1 = R.cpu().numpy(), W.cpu().numpy()
+        if greedy:
+            changed = np.nonzero(np.any(W1 != W0, axis=1))[0]
+            blk = int(changed[0] // w.b)
+            assert changed[-1] // w.b == blk
+            norms = apo.block_norms(p, R0.astype(np.float64))
+            best = int(np.argmax(norms))
+            # the GPU's row norms are FP32 sums: a block within that rounding of
+            # the largest norm is also the rule's choice
+            assert blk == best or norms[blk] >= norms[best] * (1.0 - 1e-5), (blk, best)
+            print(f"[fullsize] greedy pick {blk} (oracle {best}, norms {norms[blk]:.6e} / "
+                  f"{norms[best]:.6e})", flush=True)
+        else:
+            blk = blocks[k]
+        sl = p.block(blk)
+        rows = _rows(w.n, np.arange(sl.start, sl.stop), rng)
+        _check_update(p, w, R0, W0, R1, W1, blk, rows, tile)
+    del s, B, W, R
+    torch.cuda.empty_cache()
+
+
+def test_fullsize_updates_fp64_tiles_n2m():
+    w = gen.c3()
+    _run(w, ap.TILE_FP64, blocks=[0, w.m // 2, w.m - 1])
+
+
+def test_fullsize_greedy_updates_split_tiles_n4m():
+    _run(gen.c4(), ap.TILE_SPLIT)
