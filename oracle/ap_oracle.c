@@ -387,6 +387,81 @@ void apo_predict(const apo_config* c, const double* X, const double* W, const do
   }
 }
 
+#define APO_MAX_D 64
+
+/* ---- stochastic MLL gradient (Section 2, eq. loss_grad_unbiased) ---------- */
+
+/* Derivative factor of the kernel in r: dk/dell_m = g(r) * (x_m - x'_m)^2 / ell_m^3
+ * with g = k for RBF, 3 s exp(-sqrt3 r) for Matern-3/2 and
+ * (5/3) s (1 + sqrt5 r) exp(-sqrt5 r) for Matern-5/2 (chain rule through
+ * r^2 = sum_m ((x_m - x'_m) / ell_m)^2). */
+static double apo_dk_factor(const apo_config* c, double r2) {
+  double s = c->outputscale;
+  switch (c->kernel) {
+    case APO_RBF:
+      return s * exp(-0.5 * r2);
+    case APO_MATERN32:
+      return 3.0 * s * exp(-sqrt(3.0) * sqrt(r2));
+    case APO_MATERN52: {
+      double r = sqrt(r2);
+      return (5.0 / 3.0) * s * (1.0 + sqrt(5.0) * r) * exp(-sqrt(5.0) * r);
+    }
+    default:
+      return NAN;
+  }
+}
+
+/* The estimate of d ell / d theta for theta = (ell_1..ell_d, s, sigma^2), the
+ * negative log marginal likelihood ell = (y^T K^^{-1} y + log det K^) / 2,
+ * from W = K^^{-1} B with B = [y, z_1, ..., z_P] (P = l - 1 probes with zero
+ * mean and identity covariance):
+ *   grad_theta = -1/2 w_0^T (dK^/dtheta) w_0 + 1/(2P) sum_p w_p^T (dK^/dtheta) z_p
+ *             = sum_{i,j} C_ij (dK^/dtheta)_ij,
+ *   C_ij = -1/2 W_i0 W_j0 + 1/(2P) sum_p W_ip B_jp,
+ * with dK^/dell_m as above, dK^/ds = K / s, dK^/dsigma^2 = I. Sums over rows
+ * i in [i0, i1) and all columns j; out has d + 2 entries. */
+void apo_mll_grad_rows(const apo_config* c, const double* X, const double* B, const double* W,
+                       int64_t i0, int64_t i1, double* out) {
+  int32_t d = c->d, l = c->l, P = l - 1;
+  if (d > APO_MAX_D) {
+    for (int32_t m = 0; m < d + 2; ++m) out[m] = NAN;
+    return;
+  }
+  double acc[APO_MAX_D + 2];
+  for (int32_t m = 0; m < d + 2; ++m) acc[m] = 0.0;
+#pragma omp parallel
+  {
+    double loc[APO_MAX_D + 2];
+    for (int32_t m = 0; m < d + 2; ++m) loc[m] = 0.0;
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t i = i0; i < i1; ++i) {
+      const double* xi = X + i * d;
+      for (int64_t j = 0; j < c->n; ++j) {
+        const double* xj = X + j * d;
+        double cij = -0.5 * W[i * l] * W[j * l];
+        for (int32_t p = 1; p <= P; ++p) cij += W[i * l + p] * B[j * l + p] / (2.0 * P);
+        double r2 = apo_r2(c, xi, xj);
+        double g = apo_dk_factor(c, r2);
+        for (int32_t m = 0; m < d; ++m) {
+          double dm = xi[m] - xj[m];
+          double ell = c->lengthscale[m];
+          loc[m] += cij * g * dm * dm / (ell * ell * ell);
+        }
+        loc[d] += cij * apo_kernel(c, xi, xj) / c->outputscale;
+        if (i == j) loc[d + 1] += cij;
+      }
+    }
+#pragma omp critical
+    for (int32_t m = 0; m < d + 2; ++m) acc[m] += loc[m];
+  }
+  for (int32_t m = 0; m < d + 2; ++m) out[m] = acc[m];
+}
+
+void apo_mll_grad(const apo_config* c, const double* X, const double* B, const double* W,
+                  double* out) {
+  apo_mll_grad_rows(c, X, B, W, 0, c->n, out);
+}
+
 /* B - K^ W over all rows. */
 void apo_residual(const apo_config* c, const double* X, const double* B, const double* W,
                   double* out) {

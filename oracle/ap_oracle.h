@@ -59,6 +59,10 @@ void apo_residual_rows(const apo_config* c, const double* X, const double* B, co
                        const int64_t* rows, int64_t nrows, double* out);
 void apo_predict(const apo_config* c, const double* X, const double* W, const double* Xs,
                  int64_t ns, double* out);
+void apo_mll_grad_rows(const apo_config* c, const double* X, const double* B, const double* W,
+                       int64_t i0, int64_t i1, double* out);
+void apo_mll_grad(const apo_config* c, const double* X, const double* B, const double* W,
+                  double* out);
 void apo_residual(const apo_config* c, const double* X, const double* B, const double* W,
                   double* out);
 

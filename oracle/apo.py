@@ -77,6 +77,8 @@ def _load():
             "apo_residual_rows": (None, [C, P, P, P, P, I64, P]),
             "apo_residual": (None, [C, P, P, P, P]),
             "apo_predict": (None, [C, P, P, P, I64, P]),
+            "apo_mll_grad_rows": (None, [C, P, P, P, I64, I64, P]),
+            "apo_mll_grad": (None, [C, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -318,6 +320,20 @@ def predict(p: Problem, W: np.ndarray, Xs: np.ndarray) -> np.ndarray:
     out = np.empty((Xs.shape[0], p.l))
     c = p.cfg()
     _load().apo_predict(ctypes.byref(c), _p(p.X), _p(W), _p(Xs), Xs.shape[0], _p(out))
+    return out
+
+
+def mll_grad(p: Problem, W: np.ndarray, rows: tuple[int, int] | None = None) -> np.ndarray:
+    """Stochastic estimate of the negative log marginal likelihood's gradient
+    in (lengthscales, outputscale, noise) from W = K^^{-1} B, B = [y, probes]
+    (Section 2, eq. loss_grad_unbiased); rows = (i0, i1) sums only those rows
+    of the double sum."""
+    W = _f64(W)
+    out = np.empty(p.d + 2)
+    c = p.cfg()
+    i0, i1 = rows if rows is not None else (0, p.n)
+    _load().apo_mll_grad_rows(ctypes.byref(c), _p(p.X), _p(p.B), _p(W), int(i0), int(i1),
+                              _p(out))
     return out
 
 

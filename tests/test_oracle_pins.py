@@ -402,3 +402,54 @@ def test_posterior_mean_at_training_points_closed_form():
                     outputscale=0.8, noise=0.02, b=64)
     W = np.linalg.solve(dense_khat(p), B)
     np.testing.assert_allclose(apo.predict(p, W, X), B - 0.02 * W, rtol=0, atol=1e-10)
+
+
+def _neg_mll(X, y, kernel, ls, s, noise):
+    p = apo.Problem(X=X, B=y[:, None].copy(), kernel=kernel, lengthscale=ls, outputscale=s,
+                    noise=noise, b=X.shape[0])
+    K = dense_khat(p)
+    sign, logdet = np.linalg.slogdet(K)
+    assert sign > 0
+    return 0.5 * (y @ np.linalg.solve(K, y) + logdet)
+
+
+@pytest.mark.parametrize("kernel", [apo.RBF, apo.MATERN32, apo.MATERN52])
+def test_mll_gradient_matches_finite_differences(kernel):
+    """With the probes z_i = sqrt(n) e_i (all n of them: zero mean is not
+    needed for the identity covariance of the full set), the estimate's trace
+    term is the exact tr(K^^{-1} dK^), so the estimate is the exact gradient of
+    (y^T K^^{-1} y + log det K^) / 2 in the lengthscales, outputscale and noise:
+    pinned to central differences of that function (dense numpy)."""
+    rng = np.random.default_rng(31)
+    n, d = 24, 2
+    X = rng.uniform(size=(n, d))
+    y = np.sin(4.0 * X.sum(1)) + 0.1 * rng.standard_normal(n)
+    ls, s, noise = np.array([0.35, 0.6]), 1.4, 0.08
+    B = np.concatenate([y[:, None], np.sqrt(n) * np.eye(n)], axis=1)
+    p = apo.Problem(X=X, B=B, kernel=kernel, lengthscale=ls, outputscale=s, noise=noise, b=n)
+    W = np.linalg.solve(dense_khat(p), B)
+    got = apo.mll_grad(p, W)
+    fd = np.empty(d + 2)
+    h = 1e-6
+    for m in range(d):
+        e = np.zeros(d)
+        e[m] = h
+        fd[m] = (_neg_mll(X, y, kernel, ls + e, s, noise)
+                 - _neg_mll(X, y, kernel, ls - e, s, noise)) / (2 * h)
+    fd[d] = (_neg_mll(X, y, kernel, ls, s + h, noise) - _neg_mll(X, y, kernel, ls, s - h, noise)) / (2 * h)
+    fd[d + 1] = (_neg_mll(X, y, kernel, ls, s, noise + h)
+                 - _neg_mll(X, y, kernel, ls, s, noise - h)) / (2 * h)
+    np.testing.assert_allclose(got, fd, rtol=1e-6, atol=1e-6 * np.abs(fd).max())
+
+
+def test_mll_gradient_row_split_adds_up():
+    rng = np.random.default_rng(32)
+    n = 90
+    X = rng.uniform(size=(n, 3))
+    B = np.concatenate([rng.standard_normal((n, 1)), rng.choice([-1.0, 1.0], size=(n, 4))], 1)
+    p = apo.Problem(X=X, B=B, kernel=apo.MATERN32, lengthscale=np.array([0.3, 0.5, 0.7]),
+                    outputscale=0.9, noise=0.05, b=30)
+    W = np.linalg.solve(dense_khat(p), B)
+    full = apo.mll_grad(p, W)
+    parts = sum(apo.mll_grad(p, W, rows=(i, min(i + 17, n))) for i in range(0, n, 17))
+    np.testing.assert_allclose(parts, full, rtol=1e-12, atol=1e-12 * np.abs(full).max())
