@@ -193,6 +193,22 @@ ap_status ap_solve(ap_handle h, const ap_state* st, hipStream_t stream, ap_stats
 ap_status ap_residual(ap_handle h, const ap_state* st, float* R_out, double* col_rel,
                       hipStream_t stream);
 
+/* Stochastic gradient of the negative log marginal likelihood
+ * (y^T K^^{-1} y + log det K^) / 2 (Section 2, eq. loss_grad_unbiased) from a
+ * solve's W = K^^{-1} B, where B = [y, z_1, .., z_P] holds the targets and
+ * P = l - 1 probe vectors (zero mean, identity covariance, e.g. Rademacher):
+ *   grad_theta = -1/2 w_0^T (dK^/dtheta) w_0 + 1/(2P) sum_p w_p^T (dK^/dtheta) z_p
+ * (the second term absent when l = 1), for theta = the d lengthscales, the
+ * outputscale and the noise, over all n^2 kernel entries in FP64 without
+ * storing any of them.
+ *  grad     [host] d + 2 values: d/d ell_1 .. d/d ell_d, d/ds, d/d sigma^2.
+ *  partials [dev, may be NULL] ceil(n/64) x 22 FP64: the same sums over each
+ *           64-row slice of the double sum (columns d + 2 .. 21 zero), whose
+ *           sum in row order is grad.
+ * Synchronizes the stream. AP_ERR_NONFINITE if a component is not finite. */
+ap_status ap_mll_grad(ap_handle h, const ap_state* st, double* grad, double* partials,
+                      hipStream_t stream);
+
 /* Posterior mean at test points (Section 2, GP regression): with weights
  * W = K^^{-1} B from a solve, mean = K(X*, X) W, the test points' kernel
  * against the training points (no noise term). FP64 kernel values (exact

@@ -28,7 +28,7 @@ ERR_WORKSPACE, ERR_HIP, ERR_UNSUPPORTED = -4, -5, -6
 SYMBOLS = ("ap_workspace_bytes", "ap_factor_blocks", "ap_reset", "ap_epoch", "ap_update",
            "ap_rel_residual", "ap_solve", "ap_residual", "ap_block_inverse", "ap_set_tile",
            "ap_profile",
-           "ap_profile_read", "ap_predict", "ap_batch_step", "ap_batch_peek", "ap_batch_release",
+           "ap_profile_read", "ap_predict", "ap_mll_grad", "ap_batch_step", "ap_batch_peek", "ap_batch_release",
            "ap_destroy", "ap_status_str", "ap_last_error")
 PHASES = ("block_solve", "fused_update", "select", "epoch_check", "true_residual")
 
@@ -124,6 +124,7 @@ def load():
             "ap_residual": (I32, [P, S, P, D, P]),
             "ap_block_inverse": (I32, [P, I32, P, P]),
             "ap_predict": (I32, [P, P, P, I64, P, P]),
+            "ap_mll_grad": (I32, [P, S, D, P, P]),
             "ap_set_tile": (I32, [P, I32]),
             "ap_profile": (I32, [P, I32]),
             "ap_profile_read": (I32, [P, P, D, ctypes.POINTER(I64)]),
@@ -331,6 +332,22 @@ class Solver:
                                  ctypes.c_void_p(Xs.data_ptr()), ns,
                                  ctypes.c_void_p(out.data_ptr()), _stream(stream)), "ap_predict")
         return out
+
+    def mll_grad(self, B, W, R, partials: bool = False, stream=None):
+        """Stochastic gradient of the negative log marginal likelihood in
+        (lengthscales, outputscale, noise) from W = K^^{-1} B, B = [y, probes].
+        With partials=True also returns the per-64-row partial sums (device)."""
+        import torch
+        st = self.cstate(B, W, R)
+        grad = (ctypes.c_double * (self.d + 2))()
+        part = None
+        if partials:
+            part = torch.zeros(((self.n + 63) // 64, 22), dtype=torch.float64, device=W.device)
+        _check(load().ap_mll_grad(self.handle, ctypes.byref(st), grad,
+                                  ctypes.c_void_p(part.data_ptr() if part is not None else 0),
+                                  _stream(stream)), "ap_mll_grad")
+        g = np.array(grad[:], dtype=np.float64)
+        return (g, part) if partials else g
 
     def block_inverse(self, j: int, stream=None):
         import torch

@@ -447,6 +447,25 @@ ap_status ap_set_tile(ap_handle h, int32_t tile) {
   return AP_OK;
 }
 
+ap_status ap_mll_grad(ap_handle h, const ap_state* st, double* grad, double* partials,
+                      hipStream_t stream) {
+  if (!valid_handle(h) || !valid_state(st) || !grad) return AP_ERR_INVALID_ARG;
+  clear_foreign_error();
+  AP_HIP(ap::launch_mll_grad(h->L, h->D, h->P, h->X, st->B, st->W, stream));
+  if (partials)
+    AP_HIP(hipMemcpyAsync(partials, h->D.gpart,
+                          (size_t)h->L.nwg_mll * (ap::kMaxD + 2) * sizeof(double),
+                          hipMemcpyDeviceToDevice, stream));
+  ap::Ctl c;
+  ap_status r = read_ctl(h, stream, &c);
+  if (r != AP_OK) return r;
+  for (int m = 0; m < h->L.d + 2; ++m) {
+    if (!std::isfinite(c.mll_grad[m])) return AP_ERR_NONFINITE;
+    grad[m] = c.mll_grad[m];
+  }
+  return AP_OK;
+}
+
 ap_status ap_predict(ap_handle h, const double* W, const float* Xs, int64_t ns, double* mean,
                      hipStream_t stream) {
   if (!valid_handle(h) || ns < 0 || (ns > 0 && (!W || !Xs || !mean))) return AP_ERR_INVALID_ARG;

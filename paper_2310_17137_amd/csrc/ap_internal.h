@@ -38,6 +38,7 @@ struct Ctl {
   int32_t state;            // 0 runs; else why the problem is held (ap_batch_state)
   int32_t run;              // latched at the end of every batch step from state
   int32_t next_refine;      // > 0: epoch of the next true-residual hold; 0: every refine_every
+  double mll_grad[kMaxD + 2];  // last ap_mll_grad: lengthscales, outputscale, noise
 };
 
 // Block argument of the solve and update launches: >= 0 names the block;
@@ -75,7 +76,8 @@ struct Layout {
   int32_t nwg_res;       // workgroups of the true residual
   size_t off_ctl, off_xs, off_xrow, off_xcol, off_kinv, off_dinv, off_panel, off_delta,
       off_bspart, off_dtile, off_rowsq, off_colsq, off_blocknorm, off_respart, off_mupart,
-      off_desc;
+      off_desc, off_gpart;
+  int32_t nwg_mll;       // workgroups of the MLL gradient: 64 rows each
   size_t total;
 };
 
@@ -95,6 +97,7 @@ struct Dev {  // device pointers into one problem's workspace
   double* blocknorm;     // m block norms ||R_I||_F^2
   double* respart;       // nwg_res x 32 FP64 column partials of the true residual
   double* mupart;        // feature-centre partial sums
+  double* gpart;         // nwg_mll x (kMaxD + 2) partial sums of the MLL gradient
 };
 
 struct Params {  // hyperparameters as the kernels need them
@@ -158,6 +161,10 @@ hipError_t launch_residual(const Layout& L, const Dev& D, const Params& P, const
                            hipStream_t st);
 hipError_t launch_copy_inverse(const Layout& L, const Dev& D, int32_t j, double* dst,
                                hipStream_t st);
+// stochastic MLL gradient from W = K^^{-1} [y, probes]: per-64-row partials
+// into D.gpart, their fixed-order sum into ctl->mll_grad
+hipError_t launch_mll_grad(const Layout& L, const Dev& D, const Params& P, const float* X,
+                           const float* B, const double* W, hipStream_t st);
 // mean (ns x l, FP64) = K(Xs, X) W for ns test points Xs (ns x d, FP32)
 hipError_t launch_predict(const Layout& L, const Params& P, const float* X, const double* W,
                           const float* Xs, int64_t ns, double* mean, hipStream_t st);

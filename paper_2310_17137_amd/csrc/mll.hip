@@ -1,0 +1,190 @@
+// Stochastic gradient of the negative log marginal likelihood (Section 2,
+// eq. loss_grad_unbiased) from a solve's W = K^^{-1} B, B = [y, z_1 .. z_P]:
+//   grad_theta = -1/2 w_0^T (dK^/dtheta) w_0 + 1/(2P) sum_p w_p^T (dK^/dtheta) z_p
+//             = sum_{i,j} C_ij (dK^/dtheta)_ij,
+//   C_ij = W_i . bc_j,   bc_j = [-W_j0 / 2, B_j1 / (2P), .., B_jP / (2P)],
+// for theta = the d lengthscales, the outputscale s and the noise sigma^2:
+//   dk/dell_m = g(r) (x_m - x'_m)^2 / ell_m^3,  dK^/ds = K / s,  dK^/dsigma^2 = I,
+// with g = k (RBF), 3 s e^{-sqrt3 r} (Matern-3/2), (5/3) s (1 + sqrt5 r)
+// e^{-sqrt5 r} (Matern-5/2). Every term of the double sum over n^2 pairs is
+// formed in registers in FP64 and never stored.
+//
+// Workgroup: 4 waves x 16 rows; a lane owns row lane % 16 of its wave and the
+// columns j = 4 st + lane / 16 of each 64-column slice staged in LDS (prescaled
+// features and bc). The lane keeps its row's W in registers, forms C_ij with l
+// FMAs, and accumulates d + 2 sums; the workgroup reduces them in a fixed order
+// to one partial per 64 rows, and a last kernel adds the partials in order.
+#include <algorithm>
+
+#include "ap_internal.h"
+#include "kmap64.h"
+
+namespace ap {
+namespace {
+
+constexpr int kColsG = 64;
+constexpr int kRowsG = 64;
+
+template <int KERN, int DP, int LC>
+__global__ __launch_bounds__(256) void k_mll_grad(Layout L, Params P, const float* __restrict__ X,
+                                                  const float* __restrict__ B,
+                                                  const double* __restrict__ W,
+                                                  double* __restrict__ part) {
+  constexpr int NG = DP + 2;
+  __shared__ double sx[kColsG][DP];
+  __shared__ double sb[kColsG][LC];
+  __shared__ double etab[64];
+  __shared__ double red[4][NG];
+  scaled_exp_table(etab, P.s);  // visible after the first barrier of the column loop
+  const int d = L.d, l = L.l, np = L.l - 1;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int ln = lane % 16, lg = lane / 16;
+  const int64_t i = (int64_t)blockIdx.x * kRowsG + wave * 16 + ln;
+  const bool live = i < L.n;
+  double inv_ell[DP], xi[DP], a[LC];
+#pragma unroll
+  for (int k = 0; k < DP; ++k) inv_ell[k] = k < d ? 1.0 / P.ell[k] : 0.0;
+#pragma unroll
+  for (int k = 0; k < DP; ++k) xi[k] = (live && k < d) ? (double)X[i * d + k] * inv_ell[k] : 0.0;
+#pragma unroll
+  for (int c = 0; c < LC; ++c) a[c] = (live && c < l) ? W[i * l + c] : 0.0;
+  double g[NG];
+#pragma unroll
+  for (int m = 0; m < NG; ++m) g[m] = 0.0;
+  const double inv2p = np > 0 ? 0.5 / np : 0.0;
+
+  for (int64_t j0 = 0; j0 < L.n; j0 += kColsG) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < kColsG * DP; e += 256) {
+      const int jj = e / DP, k = e % DP;
+      sx[jj][k] = (j0 + jj < L.n && k < d) ? (double)X[(j0 + jj) * d + k] * inv_ell[k] : 0.0;
+    }
+    for (int e = threadIdx.x; e < kColsG * LC; e += 256) {
+      const int jj = e / LC, c = e % LC;
+      const int64_t j = j0 + jj;
+      double v = 0.0;
+      if (j < L.n && c < l) v = c == 0 ? -0.5 * W[j * l] : (double)B[j * l + c] * inv2p;
+      sb[jj][c] = v;
+    }
+    __syncthreads();
+    for (int st = 0; st < kColsG / 4; ++st) {
+      const int jj = 4 * st + lg;
+      const int64_t j = j0 + jj;
+      double q2[DP], r2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < DP; ++k) {
+        const double q = xi[k] - sx[jj][k];
+        q2[k] = q * q;
+        r2 += q2[k];
+      }
+      double kv, gv;
+      if constexpr (KERN == 0) {
+        kv = scaled_exp(-0.5 * r2, etab);
+        gv = kv;
+      } else if constexpr (KERN == 1) {
+        const double t = 1.7320508075688772 * sqrt(r2);
+        const double e = scaled_exp(-t, etab);
+        kv = (1.0 + t) * e;
+        gv = 3.0 * e;
+      } else {
+        const double t = 2.23606797749979 * sqrt(r2);
+        const double e = scaled_exp(-t, etab);
+        kv = (1.0 + t + (5.0 / 3.0) * r2) * e;
+        gv = (5.0 / 3.0) * (1.0 + t) * e;
+      }
+      double cij = 0.0;
+#pragma unroll
+      for (int c = 0; c < LC; ++c) cij = fma(a[c], sb[jj][c], cij);
+      const double cg = cij * gv;
+#pragma unroll
+      for (int k = 0; k < DP; ++k) g[k] = fma(cg, q2[k], g[k]);
+      g[DP] = fma(cij, kv, g[DP]);
+      if (j == i) g[DP + 1] += cij;
+    }
+  }
+  // lanes -> wave (fixed butterfly) -> workgroup (waves in order)
+#pragma unroll
+  for (int m = 0; m < NG; ++m) {
+    double v = g[m];
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 8);
+    v += __shfl_xor(v, 16);
+    v += __shfl_xor(v, 32);
+    if (lane == 0) red[wave][m] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kMaxD + 2) {
+    const int m = threadIdx.x;
+    double v = 0.0;
+    // scale: q^2 = (dx / ell)^2 needs one more 1 / ell; K / s for the outputscale
+    if (m < d)
+      v = (((red[0][m] + red[1][m]) + red[2][m]) + red[3][m]) / P.ell[m];
+    else if (m == d)
+      v = (((red[0][DP] + red[1][DP]) + red[2][DP]) + red[3][DP]) / P.s;
+    else if (m == d + 1)
+      v = ((red[0][DP + 1] + red[1][DP + 1]) + red[2][DP + 1]) + red[3][DP + 1];
+    part[(size_t)blockIdx.x * (kMaxD + 2) + m] = v;
+  }
+}
+
+// Fixed-order sum of the per-64-row partials (one workgroup).
+__global__ __launch_bounds__(256) void k_mll_final(Layout L, const double* __restrict__ part,
+                                                   Ctl* ctl) {
+  __shared__ double red[256];
+  for (int m = 0; m < L.d + 2; ++m) {
+    double acc = 0.0;
+    for (int w = threadIdx.x; w < L.nwg_mll; w += 256) acc += part[(size_t)w * (kMaxD + 2) + m];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) ctl->mll_grad[m] = red[0];
+    __syncthreads();
+  }
+}
+
+template <int KERN, int DP>
+void launch_lc(const Layout& L, const Dev& D, const Params& P, const float* X, const float* B,
+               const double* W, hipStream_t st) {
+  const dim3 g((unsigned)L.nwg_mll), t(256);
+#define AP_MLL(LC) \
+  hipLaunchKernelGGL((k_mll_grad<KERN, DP, LC>), g, t, 0, st, L, P, X, B, W, D.gpart)
+  if (L.l <= 1) AP_MLL(1);
+  else if (L.l <= 2) AP_MLL(2);
+  else if (L.l <= 4) AP_MLL(4);
+  else if (L.l <= 8) AP_MLL(8);
+  else if (L.l <= 16) AP_MLL(16);
+  else AP_MLL(32);
+#undef AP_MLL
+}
+
+template <int KERN>
+void launch_dp(const Layout& L, const Dev& D, const Params& P, const float* X, const float* B,
+               const double* W, hipStream_t st) {
+  switch (L.dp) {
+    case 4: launch_lc<KERN, 4>(L, D, P, X, B, W, st); break;
+    case 8: launch_lc<KERN, 8>(L, D, P, X, B, W, st); break;
+    case 12: launch_lc<KERN, 12>(L, D, P, X, B, W, st); break;
+    case 16: launch_lc<KERN, 16>(L, D, P, X, B, W, st); break;
+    default: launch_lc<KERN, 20>(L, D, P, X, B, W, st); break;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_mll_grad(const Layout& L, const Dev& D, const Params& P, const float* X,
+                           const float* B, const double* W, hipStream_t st) {
+  switch (L.kernel) {
+    case 0: launch_dp<0>(L, D, P, X, B, W, st); break;
+    case 1: launch_dp<1>(L, D, P, X, B, W, st); break;
+    default: launch_dp<2>(L, D, P, X, B, W, st); break;
+  }
+  hipLaunchKernelGGL(k_mll_final, dim3(1), dim3(256), 0, st, L, D.gpart, D.ctl);
+  return hipGetLastError();
+}
+
+}  // namespace ap

@@ -54,6 +54,8 @@ bool make_layout(int64_t n, int32_t d, int32_t l, int32_t b, int32_t kernel, int
   o.off_respart = take((size_t)std::max(o.nwg_res, 1024) * kMaxL * sizeof(double));
   o.off_mupart = take((size_t)256 * kMaxD * sizeof(double));
   o.off_desc = take(sizeof(Desc));
+  o.nwg_mll = (int32_t)((n + 63) / 64);
+  o.off_gpart = take((size_t)o.nwg_mll * (kMaxD + 2) * sizeof(double));
   o.total = off;
   *L = o;
   return true;
@@ -77,6 +79,7 @@ Dev bind(const Layout& L, void* ws) {
   D.blocknorm = (double*)(base + L.off_blocknorm);
   D.respart = (double*)(base + L.off_respart);
   D.mupart = (double*)(base + L.off_mupart);
+  D.gpart = (double*)(base + L.off_gpart);
   return D;
 }
 
