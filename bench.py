@@ -227,6 +227,46 @@ def bench_predict(w, make, args):
     print(json.dumps(out), flush=True)
 
 
+def bench_mll_grad(w, make, B, args):
+    """Stochastic MLL gradient (d + 2 components) from W = K^^{-1} B over all n^2
+    entries; W ~ N(0, 1) in FP64 (the rate does not depend on W); the oracle
+    on a 64-row slice of the double sum, on this host, beside it."""
+    import torch
+    from paper_2310_17137_amd import ap
+    s, t_factor = make(ap.TILE_FP64)
+    rng = np.random.default_rng(6)
+    Wh = rng.standard_normal((w.n, w.l))
+    W = torch.from_numpy(Wh).cuda()
+    R = torch.empty_like(B)
+    g = s.mll_grad(B, W, R)  # warm-up
+    reps = max(1, args.steps)
+    t0 = time.perf_counter()
+    for i in range(reps):
+        g = s.mll_grad(B, W, R)
+        log(f"[mll] call {i + 1} of {reps} done at {time.perf_counter() - t0:.2f} s")
+    dt = (time.perf_counter() - t0) / reps
+    cpu = None
+    if not args.no_cpu:
+        from oracle import apo
+        p = apo.Problem(X=w.X.astype(np.float64), B=w.B.astype(np.float64), kernel=w.kernel,
+                        lengthscale=w.lengthscale, outputscale=w.outputscale, noise=w.noise,
+                        b=w.b)
+        t1 = time.perf_counter()
+        apo.mll_grad(p, Wh, rows=(0, 64))
+        tc = time.perf_counter() - t1
+        per = tc * (w.n / 64.0)
+        cpu = {"value": 1.0 / per, "unit": "gradients/s", "cores": apo.num_threads(),
+               "kind": "oracle", "sample": f"64 of {w.n} rows of the double sum in {tc:.1f} s, "
+                                           f"scaled by n / 64"}
+    out = {"metric": "stochastic MLL gradients/s", "value": 1.0 / dt, "unit": "gradients/s",
+           "n_gpus": 1, "steps": reps, "warmup": 1, "ms_per_step": dt * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic", "config": {"workload": describe(w), "probes": w.l - 1},
+           "kernel_entries_per_s": float(w.n) * w.n / dt, "gradient": g.tolist(),
+           "factor_s": t_factor, "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap_ = argparse.ArgumentParser()
     ap_.add_argument("--gpus", type=int, default=1)
@@ -244,11 +284,17 @@ def main():
                      help="comma-separated tile paths: run ap_solve on each (reset, epochs, "
                           "FP64 true-residual refinement and confirmation) and print the time "
                           "to the tolerance instead of the epoch-rate line")
+    ap_.add_argument("--b", type=int, default=0, help="override the workload's block size")
+    ap_.add_argument("--order", default="", choices=["", "cyclic", "greedy"],
+                     help="override the workload's block selection")
     ap_.add_argument("--max-epochs", type=int, default=0,
                      help="with --time-to-tol: epoch limit (0: the workload's)")
     ap_.add_argument("--predict", type=int, default=-1,
                      help="time the posterior mean (ap_predict) at this many test points "
                           "(0: n/4, the paper's 80/20 split) instead of the epoch-rate line")
+    ap_.add_argument("--mll-grad", action="store_true",
+                     help="time the stochastic MLL gradient (ap_mll_grad) instead of the "
+                          "epoch-rate line")
     ap_.add_argument("--copy-calibration", action="store_true",
                      help="only run a 1 GiB device-to-device copy (HBM counter calibration)")
     args = ap_.parse_args()
@@ -273,6 +319,10 @@ def main():
     ap.load()
     t = time.perf_counter()
     w = workload(args.workload)
+    if args.b > 0:
+        w.b = args.b
+    if args.order:
+        w.order = 1 if args.order == "greedy" else 0
     log(f"[bench] generated {describe(w)} in {time.perf_counter() - t:.1f} s")
 
     X = torch.from_numpy(w.X).to(dev)
@@ -291,6 +341,9 @@ def main():
 
     if args.predict >= 0:
         bench_predict(w, make, args)
+        return
+    if args.mll_grad:
+        bench_mll_grad(w, make, B, args)
         return
 
     if args.time_to_tol:

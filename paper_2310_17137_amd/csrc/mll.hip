@@ -9,11 +9,15 @@
 // e^{-sqrt5 r} (Matern-5/2). Every term of the double sum over n^2 pairs is
 // formed in registers in FP64 and never stored.
 //
-// Workgroup: 4 waves x 16 rows; a lane owns row lane % 16 of its wave and the
-// columns j = 4 st + lane / 16 of each 64-column slice staged in LDS (prescaled
-// features and bc). The lane keeps its row's W in registers, forms C_ij with l
-// FMAs, and accumulates d + 2 sums; the workgroup reduces them in a fixed order
-// to one partial per 64 rows, and a last kernel adds the partials in order.
+// Workgroup: 4 waves x 16 rows; the columns are staged in LDS 64 at a time
+// (prescaled features and bc, padded to a multiple of 4). C_ij for a 16 x 16
+// tile of pairs is the rank-l product W_tile bc_tile^T, formed on the FP64
+// matrix cores (v_mfma_f64_16x16x4f64: the wave's W rows are the A operand,
+// held in registers; bc the B operand), which leaves each lane four pairs
+// (rows lane / 16 + 4 q, column lane % 16) whose kernel value, derivative
+// factor and d + 2 sums it forms on the vector units. The workgroup reduces
+// the sums in a fixed order to one partial per 64 rows, and a last kernel adds
+// the partials in order.
 #include <algorithm>
 
 #include "ap_internal.h"
@@ -22,32 +26,49 @@
 namespace ap {
 namespace {
 
+typedef __attribute__((ext_vector_type(4))) double f64x4;
 constexpr int kColsG = 64;
 constexpr int kRowsG = 64;
 
-template <int KERN, int DP, int LC>
+template <int KERN, int DP, int KS>
 __global__ __launch_bounds__(256) void k_mll_grad(Layout L, Params P, const float* __restrict__ X,
                                                   const float* __restrict__ B,
                                                   const double* __restrict__ W,
                                                   double* __restrict__ part) {
   constexpr int NG = DP + 2;
+  constexpr int KP = 4 * KS;  // coefficients per point, padded to the matrix K step
+  constexpr int UNR = DP <= 8 ? 2 : 1;  // tiles in flight (register budget)
   __shared__ double sx[kColsG][DP];
-  __shared__ double sb[kColsG][LC];
+  __shared__ double sb[kColsG][KP];
   __shared__ double etab[64];
   __shared__ double red[4][NG];
   scaled_exp_table(etab, P.s);  // visible after the first barrier of the column loop
   const int d = L.d, l = L.l, np = L.l - 1;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int ln = lane % 16, lg = lane / 16;
-  const int64_t i = (int64_t)blockIdx.x * kRowsG + wave * 16 + ln;
-  const bool live = i < L.n;
-  double inv_ell[DP], xi[DP], a[LC];
+  const int64_t row0 = (int64_t)blockIdx.x * kRowsG + wave * 16;
+  double inv_ell[DP];
 #pragma unroll
   for (int k = 0; k < DP; ++k) inv_ell[k] = k < d ? 1.0 / P.ell[k] : 0.0;
+  // A operand of v_mfma_f64_16x16x4f64: W[row0 + lane % 16][4 s + lane / 16]
+  double a[KS];
+  {
+    const int64_t i = row0 + ln;
 #pragma unroll
-  for (int k = 0; k < DP; ++k) xi[k] = (live && k < d) ? (double)X[i * d + k] * inv_ell[k] : 0.0;
+    for (int s = 0; s < KS; ++s) {
+      const int c = 4 * s + lg;
+      a[s] = (i < L.n && c < l) ? W[i * l + c] : 0.0;
+    }
+  }
+  // the lane's output pairs are rows row0 + lane / 16 + 4 q (q = 0..3)
+  double xi[4][DP];
 #pragma unroll
-  for (int c = 0; c < LC; ++c) a[c] = (live && c < l) ? W[i * l + c] : 0.0;
+  for (int q = 0; q < 4; ++q) {
+    const int64_t i = row0 + lg + 4 * q;
+#pragma unroll
+    for (int k = 0; k < DP; ++k)
+      xi[q][k] = (i < L.n && k < d) ? (double)X[i * d + k] * inv_ell[k] : 0.0;
+  }
   double g[NG];
 #pragma unroll
   for (int m = 0; m < NG; ++m) g[m] = 0.0;
@@ -59,47 +80,63 @@ __global__ __launch_bounds__(256) void k_mll_grad(Layout L, Params P, const floa
       const int jj = e / DP, k = e % DP;
       sx[jj][k] = (j0 + jj < L.n && k < d) ? (double)X[(j0 + jj) * d + k] * inv_ell[k] : 0.0;
     }
-    for (int e = threadIdx.x; e < kColsG * LC; e += 256) {
-      const int jj = e / LC, c = e % LC;
+    for (int e = threadIdx.x; e < kColsG * KP; e += 256) {
+      const int jj = e / KP, c = e % KP;
       const int64_t j = j0 + jj;
       double v = 0.0;
       if (j < L.n && c < l) v = c == 0 ? -0.5 * W[j * l] : (double)B[j * l + c] * inv2p;
       sb[jj][c] = v;
     }
     __syncthreads();
-    for (int st = 0; st < kColsG / 4; ++st) {
-      const int jj = 4 * st + lg;
+#pragma unroll UNR
+    for (int tile = 0; tile < kColsG / 16; ++tile) {
+      const int jj = 16 * tile + ln;  // this lane's column in the 16 x 16 tile
       const int64_t j = j0 + jj;
-      double q2[DP], r2 = 0.0;
+      // C[m][n] = sum_k W[row0 + m][k] bc[j0 + 16 tile + n][k]; the lane receives
+      // C at (m = lane / 16 + 4 q, n = lane % 16). Two accumulator chains.
+      f64x4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int k = 0; k < DP; ++k) {
-        const double q = xi[k] - sx[jj][k];
-        q2[k] = q * q;
-        r2 += q2[k];
+      for (int s = 0; s < KS; s += 2) {
+        c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], sb[jj][4 * s + lg], c0, 0, 0, 0);
+        if (s + 1 < KS)
+          c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s + 1], sb[jj][4 * s + 4 + lg], c1, 0, 0,
+                                                    0);
       }
-      double kv, gv;
-      if constexpr (KERN == 0) {
-        kv = scaled_exp(-0.5 * r2, etab);
-        gv = kv;
-      } else if constexpr (KERN == 1) {
-        const double t = 1.7320508075688772 * sqrt(r2);
-        const double e = scaled_exp(-t, etab);
-        kv = (1.0 + t) * e;
-        gv = 3.0 * e;
-      } else {
-        const double t = 2.23606797749979 * sqrt(r2);
-        const double e = scaled_exp(-t, etab);
-        kv = (1.0 + t + (5.0 / 3.0) * r2) * e;
-        gv = (5.0 / 3.0) * (1.0 + t) * e;
+      const f64x4 cc = c0 + c1;
+      double xc[DP];
+#pragma unroll
+      for (int k = 0; k < DP; ++k) xc[k] = sx[jj][k];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        double q2[DP], r2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < DP; ++k) {
+          const double dq = xi[q][k] - xc[k];
+          q2[k] = dq * dq;
+          r2 += q2[k];
+        }
+        double kv, gv;
+        if constexpr (KERN == 0) {
+          kv = scaled_exp(-0.5 * r2, etab);
+          gv = kv;
+        } else if constexpr (KERN == 1) {
+          const double t = 1.7320508075688772 * sqrt(r2);
+          const double e = scaled_exp(-t, etab);
+          kv = (1.0 + t) * e;
+          gv = 3.0 * e;
+        } else {
+          const double t = 2.23606797749979 * sqrt(r2);
+          const double e = scaled_exp(-t, etab);
+          kv = (1.0 + t + (5.0 / 3.0) * r2) * e;
+          gv = (5.0 / 3.0) * (1.0 + t) * e;
+        }
+        const double cij = cc[q];
+        const double cg = cij * gv;
+#pragma unroll
+        for (int k = 0; k < DP; ++k) g[k] = fma(cg, q2[k], g[k]);
+        g[DP] = fma(cij, kv, g[DP]);
+        if (j == row0 + lg + 4 * q) g[DP + 1] += cij;
       }
-      double cij = 0.0;
-#pragma unroll
-      for (int c = 0; c < LC; ++c) cij = fma(a[c], sb[jj][c], cij);
-      const double cg = cij * gv;
-#pragma unroll
-      for (int k = 0; k < DP; ++k) g[k] = fma(cg, q2[k], g[k]);
-      g[DP] = fma(cij, kv, g[DP]);
-      if (j == i) g[DP + 1] += cij;
     }
   }
   // lanes -> wave (fixed butterfly) -> workgroup (waves in order)
@@ -151,14 +188,12 @@ template <int KERN, int DP>
 void launch_lc(const Layout& L, const Dev& D, const Params& P, const float* X, const float* B,
                const double* W, hipStream_t st) {
   const dim3 g((unsigned)L.nwg_mll), t(256);
-#define AP_MLL(LC) \
-  hipLaunchKernelGGL((k_mll_grad<KERN, DP, LC>), g, t, 0, st, L, P, X, B, W, D.gpart)
-  if (L.l <= 1) AP_MLL(1);
-  else if (L.l <= 2) AP_MLL(2);
-  else if (L.l <= 4) AP_MLL(4);
-  else if (L.l <= 8) AP_MLL(8);
-  else if (L.l <= 16) AP_MLL(16);
-  else AP_MLL(32);
+#define AP_MLL(KS) \
+  hipLaunchKernelGGL((k_mll_grad<KERN, DP, KS>), g, t, 0, st, L, P, X, B, W, D.gpart)
+  if (L.l <= 4) AP_MLL(1);
+  else if (L.l <= 8) AP_MLL(2);
+  else if (L.l <= 16) AP_MLL(4);
+  else AP_MLL(8);
 #undef AP_MLL
 }
 
