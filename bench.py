@@ -13,8 +13,11 @@ timing starts.
 
 Printed (one JSON line on stdout): epochs/s, the fused update's live roofline
 position from HIP events on its stream, the other tile paths' epochs/s on the
-same problem, residual ratios (maintained and FP64 true), the factor time, and
-the FP64 CPU oracle timed on a bounded sample on this host.
+same problem, residual ratios (maintained and FP64 true), the factor time, the
+time to a relative residual of 1e-2 at n = 2M for the FP64, mixed (split) and
+FP32 paths (the same inputs with the target column alone, greedy order,
+b = 4096; outside the timed epochs), and the FP64 CPU oracle timed on a
+bounded sample on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -131,6 +134,41 @@ def cpu_baseline(w, updates: int) -> dict:
             "cpu": platform.processor() or platform.machine()}
 
 
+def make_solver(w, X, tile):
+    """Factor the blocks of workload w (X on the GPU); returns (solver, seconds)."""
+    import torch
+    from paper_2310_17137_amd import ap
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = ap.Solver(X, l=w.l, b=w.b, kernel=w.kernel, lengthscale=w.lengthscale,
+                  outputscale=w.outputscale, noise=w.noise, order=w.order, tile=tile,
+                  refine_every=w.refine_every, tol=w.tol, min_epochs=w.min_epochs,
+                  max_epochs=w.max_epochs)
+    torch.cuda.synchronize()
+    return s, time.perf_counter() - t0
+
+
+def default_time_to_tol(tiles, max_epochs=60):
+    """Time to rho < 1e-2 at n = 2M: the n = 2M inputs with the target column
+    alone (the paper's test-time solve), greedy block order, b = 4096, for each
+    tile path (ap_solve with FP64 true-residual confirmation)."""
+    import torch
+    from paper_2310_17137_amd import gen
+    w = gen.c3(l=1)
+    w.b, w.order, w.max_epochs = 4096, gen.GREEDY, max_epochs
+    X = torch.from_numpy(w.X).cuda()
+    B = torch.from_numpy(w.B).cuda()
+    runs = time_to_tol(w, lambda tile: make_solver(w, X, tile), B, tiles)
+    out = {"workload": describe(w), "tol": w.tol, "max_epochs": w.max_epochs, "runs": {}}
+    for r in runs:
+        out["runs"][r["tile"]] = {k: r.get(k) for k in ("converged", "epochs", "time_to_tol_s",
+                                                         "factor_s", "t_refine", "rho_true",
+                                                         "final_tile", "escalated_at")}
+    del X, B
+    torch.cuda.empty_cache()
+    return out
+
+
 def time_to_tol(w, make, B, tiles):
     """ap_solve per tile path; a watcher thread reports the epoch and ratio
     every 20 s (ap_batch_peek reads the control block while the solve runs)."""
@@ -175,8 +213,7 @@ def time_to_tol(w, make, B, tiles):
         del s, W, R
         import torch
         torch.cuda.empty_cache()
-    print(json.dumps({"time_to_tol": runs, "workload": describe(w), "tol": w.tol,
-                      "refine_every": w.refine_every, "max_epochs": w.max_epochs}), flush=True)
+    return runs
 
 
 def bench_predict(w, make, args):
@@ -280,6 +317,8 @@ def main():
     ap_.add_argument("--cpu-updates", type=int, default=2)
     ap_.add_argument("--no-cpu", action="store_true")
     ap_.add_argument("--no-true-residual", action="store_true")
+    ap_.add_argument("--no-ttt", action="store_true",
+                     help="skip the time-to-tolerance runs of the default line")
     ap_.add_argument("--time-to-tol", default="",
                      help="comma-separated tile paths: run ap_solve on each (reset, epochs, "
                           "FP64 true-residual refinement and confirmation) and print the time "
@@ -330,14 +369,7 @@ def main():
     torch.cuda.synchronize()
 
     def make(tile):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s = ap.Solver(X, l=w.l, b=w.b, kernel=w.kernel, lengthscale=w.lengthscale,
-                      outputscale=w.outputscale, noise=w.noise, order=w.order, tile=tile,
-                      refine_every=w.refine_every, tol=w.tol, min_epochs=w.min_epochs,
-                      max_epochs=w.max_epochs)
-        torch.cuda.synchronize()
-        return s, time.perf_counter() - t0
+        return make_solver(w, X, tile)
 
     if args.predict >= 0:
         bench_predict(w, make, args)
@@ -349,7 +381,10 @@ def main():
     if args.time_to_tol:
         if args.max_epochs > 0:
             w.max_epochs = args.max_epochs
-        time_to_tol(w, make, B, args.time_to_tol.split(","))
+        runs = time_to_tol(w, make, B, args.time_to_tol.split(","))
+        print(json.dumps({"time_to_tol": runs, "workload": describe(w), "tol": w.tol,
+                          "refine_every": w.refine_every, "max_epochs": w.max_epochs}),
+              flush=True)
         return
 
     def run_path(tile, steps, warmup, want_true):
@@ -460,6 +495,12 @@ def main():
                 "issued_mfma_tflops": mfma_flops_launch / avg / 1e12,
                 "hbm_gbs": bytes_launch / avg / 1e9}
 
+    ttt = None
+    if not args.no_ttt and w.name == "c3":
+        del B, X
+        torch.cuda.empty_cache()
+        ttt = default_time_to_tol(["fp64", "split", "fp32"])
+
     cpu = None
     if not args.no_cpu and args.cpu_updates > 0:
         cpu = cpu_baseline(w, args.cpu_updates)
@@ -476,6 +517,7 @@ def main():
                    "global_batch": w.l, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "time_to_tol": ttt,
         "paths": paths,
     }
     print(json.dumps(out), flush=True)
