@@ -541,6 +541,17 @@ ap_status ap_batch_step(const ap_handle* h, const ap_state* st, int32_t count, i
     }
   }
   gp.count = gf.count = ga.count = count;
+  // greedy selection after the updates: block norms (one workgroup per block)
+  // and argmax (one per problem) of the greedy problems
+  ap::Group gsel_n{}, gsel_a{};
+  for (int32_t p = 0; p < count; ++p) {
+    if (h[p]->L.order != AP_GREEDY) continue;
+    const int32_t k = gsel_n.count++;
+    gsel_n.desc[k] = gsel_a.desc[k] = h[p]->desc_dev;
+    gsel_n.wg0[k + 1] = gsel_n.wg0[k] + h[p]->L.m;
+    gsel_a.wg0[k + 1] = gsel_a.wg0[k] + 1;
+  }
+  gsel_a.count = gsel_n.count;
   // The wide split group and the other tiles run on a second stream beside
   // the narrow group, between a fork after the solves and a join before the
   // epoch advance.
@@ -573,8 +584,7 @@ ap_status ap_batch_step(const ap_handle* h, const ap_state* st, int32_t count, i
       AP_HIP(hipEventRecord(aux->join, aux->s));
       AP_HIP(hipStreamWaitEvent(stream, aux->join, 0));
     }
-    for (int32_t p = 0; p < count; ++p)
-      if (h[p]->L.order == AP_GREEDY) AP_HIP(ap::launch_select(h[p]->L, h[p]->D, stream));
+    if (gsel_n.count > 0) AP_HIP(ap::launch_group_select(gsel_n, gsel_a, stream));
     AP_HIP(ap::launch_group_advance(ga, stream));
   }
   return AP_OK;

@@ -173,6 +173,7 @@ hipError_t launch_predict(const Layout& L, const Params& P, const float* X, cons
 hipError_t launch_group_solve(const Group& gp, const Group& gf, hipStream_t st);
 // wide: the group's feature strides are 12 to 20 (else 4 or 8)
 hipError_t launch_group_split(const Group& g, bool wide, hipStream_t st);
+hipError_t launch_group_select(const Group& gn, const Group& ga, hipStream_t st);
 hipError_t launch_group_advance(const Group& g, hipStream_t st);
 hipError_t launch_release(const Dev& D, int32_t next_refine, hipStream_t st);
 

@@ -281,10 +281,9 @@ __global__ void k_reset_final(Layout L, const double* __restrict__ part, int gro
 
 // ||R_I||_F^2 for every block from the per-row sums of squares (one workgroup
 // per block, fixed reduction order).
-__global__ __launch_bounds__(256) void k_block_norms(Layout L, const float* __restrict__ rowsq,
-                                                     double* __restrict__ out) {
+__device__ __forceinline__ void block_norm_body(const Layout& L, const float* __restrict__ rowsq,
+                                                double* __restrict__ out, int64_t j) {
   __shared__ double red[256];
-  const int64_t j = blockIdx.x;
   const int64_t s = j * L.b;
   const int64_t e = std::min<int64_t>(s + L.b, L.n);
   double acc = 0.0;
@@ -298,9 +297,14 @@ __global__ __launch_bounds__(256) void k_block_norms(Layout L, const float* __re
   if (threadIdx.x == 0) out[j] = red[0];
 }
 
+__global__ __launch_bounds__(256) void k_block_norms(Layout L, const float* __restrict__ rowsq,
+                                                     double* __restrict__ out) {
+  block_norm_body(L, rowsq, out, blockIdx.x);
+}
+
 // Modified Gauss-Southwell rule: argmax over blocks, ties to the lowest index.
-__global__ __launch_bounds__(256) void k_argmax(Layout L, const double* __restrict__ nrm,
-                                                Ctl* ctl) {
+__device__ __forceinline__ void argmax_body(const Layout& L, const double* __restrict__ nrm,
+                                            Ctl* ctl) {
   __shared__ double bv[256];
   __shared__ int bi[256];
   double best = -1.0;
@@ -327,6 +331,29 @@ __global__ __launch_bounds__(256) void k_argmax(Layout L, const double* __restri
     __syncthreads();
   }
   if (threadIdx.x == 0) ctl->sel = bi[0];
+}
+
+__global__ __launch_bounds__(256) void k_argmax(Layout L, const double* __restrict__ nrm,
+                                                Ctl* ctl) {
+  argmax_body(L, nrm, ctl);
+}
+
+// Grouped selection of a batch step for the greedy problems: one workgroup per
+// block of each problem, then one per problem for the argmax.
+__global__ __launch_bounds__(256) void g_block_norms(Group g) {
+  int wg;
+  const int p = group_job(g, &wg);
+  const Desc* ds = g.desc[p];
+  const Layout L = ds->L;
+  block_norm_body(L, ds->D.rowsq, ds->D.blocknorm, wg);
+}
+
+__global__ __launch_bounds__(256) void g_argmax(Group g) {
+  int wg;
+  const int p = group_job(g, &wg);
+  const Desc* ds = g.desc[p];
+  const Layout L = ds->L;
+  argmax_body(L, ds->D.blocknorm, ds->D.ctl);
 }
 
 // Epoch-end check (Section 5, "Alternating Projection Details"): column norms
@@ -450,6 +477,12 @@ hipError_t launch_reset(const Layout& L, const Dev& D, const float* B, double* W
 hipError_t launch_select(const Layout& L, const Dev& D, hipStream_t st) {
   hipLaunchKernelGGL(k_block_norms, dim3(L.m), dim3(256), 0, st, L, D.rowsq, D.blocknorm);
   hipLaunchKernelGGL(k_argmax, dim3(1), dim3(256), 0, st, L, D.blocknorm, D.ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_select(const Group& gn, const Group& ga, hipStream_t st) {
+  hipLaunchKernelGGL(g_block_norms, dim3(gn.wg0[gn.count]), dim3(256), 0, st, gn);
+  hipLaunchKernelGGL(g_argmax, dim3(ga.count), dim3(256), 0, st, ga);
   return hipGetLastError();
 }
 

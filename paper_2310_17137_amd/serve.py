@@ -86,7 +86,7 @@ class Server:
     def __init__(self, budget_bytes: float = 200e9, max_active: int = 16,
                  tile: int = ap.TILE_SPLIT, refine_every: int = 5, steps_per_call: int = 4,
                  max_epochs: int = 1000, tol: float = 1e-2, keep_w: bool = False,
-                 device: str = "cuda"):
+                 order: int | None = None, device: str = "cuda"):
         import torch
         self.torch = torch
         self.budget = float(budget_bytes)
@@ -99,6 +99,7 @@ class Server:
         self.max_epochs = int(max_epochs)
         self.tol = float(tol)
         self.keep_w = keep_w
+        self.order = order  # block selection for every request (None: the request's own)
         self.device = torch.device(device)
         self.peak_bytes = 0
         self.peak_active = 0
@@ -112,7 +113,8 @@ class Server:
             X = torch.from_numpy(w.X).to(self.device, non_blocking=False)
             B = torch.from_numpy(w.B).to(self.device, non_blocking=False)
             s = ap.Solver(X, l=w.l, b=w.b, kernel=w.kernel, lengthscale=w.lengthscale,
-                          outputscale=w.outputscale, noise=w.noise, order=w.order,
+                          outputscale=w.outputscale, noise=w.noise,
+                          order=w.order if self.order is None else self.order,
                           tile=self.tile, refine_every=self.refine_every, tol=self.tol,
                           max_epochs=self.max_epochs, stream=adm)  # factors, syncs `adm`
             W, R = s.new_state(B)
@@ -316,6 +318,8 @@ def main(argv=None):
     p.add_argument("--budget-gb", type=float, default=200.0)
     p.add_argument("--tile", default="split", choices=["split", "fp32", "fp64", "bf16"])
     p.add_argument("--refine-every", type=int, default=5)
+    p.add_argument("--order", default="request", choices=["request", "cyclic", "greedy"],
+                   help="block selection (request: each request's own)")
     p.add_argument("--steps-per-call", type=int, default=4,
                    help="batch steps enqueued per ap_batch_step call")
     p.add_argument("--seed", type=int, default=0)
@@ -330,7 +334,8 @@ def main(argv=None):
     def serve_once(reqs, label, rate):
         srv = Server(budget_bytes=a.budget_gb * 1e9, max_active=a.max_active, tile=tile,
                      refine_every=a.refine_every, max_epochs=a.max_epochs,
-                     steps_per_call=a.steps_per_call)
+                     steps_per_call=a.steps_per_call,
+                     order={"request": None, "cyclic": gen.CYCLIC, "greedy": gen.GREEDY}[a.order])
         t = time.perf_counter()
         done = srv.run(reqs, log=log)
         out = summarize(done, time.perf_counter() - t)
@@ -343,6 +348,7 @@ def main(argv=None):
         out.update({"run": label, "rate": rate, "peak_active": srv.peak_active,
                     "peak_gb": srv.peak_bytes / 1e9, "count": a.count, "n_min": a.n_min,
                     "n_max": a.n_max, "max_epochs": a.max_epochs, "tile": a.tile,
+                    "order": a.order,
                     "batch_steps": srv.batch_steps})
         print(json.dumps(out), flush=True)
         return out
