@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void k_mll_grad(Layout L, Params P, const floa
   constexpr int UNR = DP <= 8 ? 2 : 1;  // tiles in flight (register budget)
   __shared__ double sx[kColsG][DP];
   __shared__ double sb[kColsG][KP];
-  __shared__ double etab[64];
+  __shared__ double etab[kExpTab];
   __shared__ double red[4][NG];
   scaled_exp_table(etab, P.s);  // visible after the first barrier of the column loop
   const int d = L.d, l = L.l, np = L.l - 1;
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void k_mll_grad(Layout L, Params P, const floa
         }
         double kv, gv;
         if constexpr (KERN == 0) {
-          kv = scaled_exp(-0.5 * r2, etab);
+          kv = scaled_exp_nhalf(r2, etab);
           gv = kv;
         } else if constexpr (KERN == 1) {
           const double t = 1.7320508075688772 * sqrt(r2);

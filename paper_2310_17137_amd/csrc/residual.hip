@@ -37,7 +37,7 @@ __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const floa
   __shared__ double sx[kCols][DP];
   __shared__ double sw[kCols][16 * NH];
   __shared__ double red[4][16 * NH];
-  __shared__ double etab[64];  // s * 2^(j/64) for the exponential
+  __shared__ double etab[kExpTab];  // s * 2^(j/256) for the exponential
   scaled_exp_table(etab, P.s);  // visible after the first barrier of the column loop
   const int d = L.d, l = L.l;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
@@ -171,7 +171,7 @@ __global__ __launch_bounds__(256) void k_residualv(Layout L, Params P, const flo
   __shared__ double sx[kCols][DP];
   __shared__ double sw[kCols][NV];
   __shared__ double red[4][kMaxL];
-  __shared__ double etab[64];  // s * 2^(j/64) for the exponential
+  __shared__ double etab[kExpTab];  // s * 2^(j/256) for the exponential
   scaled_exp_table(etab, P.s);  // visible after the first barrier of the column loop
   const int d = L.d, l = L.l;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;

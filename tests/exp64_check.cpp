@@ -3,6 +3,7 @@
 // the last place of the FP64 result over a dense sweep of arguments.
 #include <cmath>
 #include <cstdio>
+#include <cstring>
 #include <random>
 
 #include "../paper_2310_17137_amd/csrc/kmap64.h"
@@ -20,8 +21,8 @@ int main() {
   double worst_y = 0.0;
   std::mt19937_64 rng(7);
   for (double s : scales) {
-    double tab[64];
-    for (int j = 0; j < 64; ++j) tab[j] = s * ap::kExp2Tab[j];
+    double tab[ap::kExpTab];
+    for (int j = 0; j < ap::kExpTab; ++j) tab[j] = s * ap::kExp2Tab[j];
     // the exponential: y in [-700, 0] (normal results), uniform and dense near 0
     std::uniform_real_distribution<double> wide(-700.0, 0.0), near(-1.0, 0.0);
     for (int i = 0; i < 400000; ++i) {
@@ -29,7 +30,8 @@ int main() {
       const double e = ulps(ap::scaled_exp(y, tab), (long double)s * expl((long double)y));
       if (e > worst_exp) { worst_exp = e; worst_y = y; }
     }
-    for (double y : {0.0, -1e-300, -1e-17, -0x1p-60, -0.0054, -0.0108, -0.5, -1.0, -10.0}) {
+    for (double y : {0.0, -1e-300, -1e-17, -0x1p-60, -0.00135, -0.0027, -0.0054, -0.5, -1.0,
+                     -10.0}) {
       const double e = ulps(ap::scaled_exp(y, tab), (long double)s * expl((long double)y));
       if (e > worst_exp) { worst_exp = e; worst_y = y; }
     }
@@ -54,8 +56,26 @@ int main() {
       if (k1 > 1e-300L && n1 > worst_map[1]) worst_map[1] = n1;
       if (k2 > 1e-300L && n2 > worst_map[2]) worst_map[2] = n2;
     }
-    double tab1[64];
-    for (int j = 0; j < 64; ++j) tab1[j] = ap::kExp2Tab[j];
+    // the RBF form with the halving folded into the constants is bitwise the
+    // general one at -r2 / 2, above the FP64 range's end and beyond
+    for (int i = 0; i < 400000; ++i) {
+      const double r2 = (i % 4 == 0) ? r2d(rng) : (i % 4 == 1) ? r2n(rng)
+                        : (i % 4 == 2) ? std::ldexp(r2n(rng), -(i % 1000)) : 1400.0 + r2n(rng) * 30.0;
+      const double a = ap::scaled_exp_nhalf(r2, tab), b = ap::scaled_exp(-0.5 * r2, tab);
+      if (std::memcmp(&a, &b, sizeof a) != 0) {
+        std::printf("nhalf mismatch at r2 %.17g: %.17g vs %.17g\n", r2, a, b);
+        return 1;
+      }
+    }
+    for (double r2 : {0.0, 1e-300, 1492.0, 1493.0, 3000.0, 1e300, (double)INFINITY}) {
+      const double a = ap::scaled_exp_nhalf(r2, tab), b = ap::scaled_exp(-0.5 * r2, tab);
+      if (std::memcmp(&a, &b, sizeof a) != 0) {
+        std::printf("nhalf mismatch at r2 %.17g: %.17g vs %.17g\n", r2, a, b);
+        return 1;
+      }
+    }
+    double tab1[ap::kExpTab];
+    for (int j = 0; j < ap::kExpTab; ++j) tab1[j] = ap::kExp2Tab[j];
     // below the FP64 range the result is 0 or subnormal, never garbage
     for (double y : {-745.0, -745.2, -746.0, -800.0, -1e6, -1e300}) {
       const double v = ap::scaled_exp(y, tab1);
