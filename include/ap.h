@@ -64,9 +64,15 @@ typedef enum { AP_RBF = 0, AP_MATERN32 = 1, AP_MATERN52 = 2 } ap_kernel;
 
 /* Block selection (Section 3, "Block Selection"): AP_CYCLIC takes block
  * (u mod m) at update u of every epoch, starting at block 0; AP_GREEDY takes
- * argmax_I ||R_{I,:}||_F^2, ties to the lowest block index; an epoch is m
- * selections either way. */
-typedef enum { AP_CYCLIC = 0, AP_GREEDY = 1 } ap_order;
+ * argmax_I ||R_{I,:}||_F^2, ties to the lowest block index; AP_RANDOM draws
+ * I uniformly from the partition: update u since the last reset (counted
+ * over epochs) takes block floor(h * m / 2^32), h the high 32 bits of output
+ * u of SplitMix64 (Steele, Lea and Flood, OOPSLA 2014) started from the
+ * config's seed, i.e. of z = seed + (u + 1) * 0x9e3779b97f4a7c15 after
+ * z ^= z >> 30, z *= 0xbf58476d1ce4e5b9, z ^= z >> 27,
+ * z *= 0x94d049bb133111eb, z ^= z >> 31. An epoch is m selections in all
+ * three. ap_update with an explicit block does not consume a draw. */
+typedef enum { AP_CYCLIC = 0, AP_GREEDY = 1, AP_RANDOM = 2 } ap_order;
 
 /* Arithmetic of the fused residual update (the kernel tiles K^_{:,I} and their
  * product with the block step). Block factors, block solves, W and the true
@@ -105,6 +111,7 @@ typedef struct {
   double tol;                 /* ap_solve: stop when the ratio is < tol */
   int32_t min_epochs;         /* ap_solve: never stop before this many epochs */
   int32_t max_epochs;         /* ap_solve: stop after this many epochs */
+  uint64_t seed;              /* AP_RANDOM: seed of the block draws (else unused) */
 } ap_config;
 
 /* Per-problem device state, all [dev], n x l row-major:

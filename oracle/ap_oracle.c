@@ -27,7 +27,8 @@
  *  - partition: block j holds rows [j b, min((j+1) b, n)), the last block is
  *    the remainder ("Cached Cholesky Factors", "Alternating Projection Details");
  *  - cyclic order starts at block 0 in every epoch; the greedy rule breaks ties
- *    towards the lowest block index; a greedy epoch is m selections;
+ *    towards the lowest block index; the random rule draws each update's block
+ *    from SplitMix64 (below); an epoch is m selections in every order;
  *  - stopping: mean over columns of ||r_c|| / ||b_c||, strictly below tol, after
  *    at least min_epochs epochs, or at max_epochs ("Alternating Projection
  *    Details"); a column with ||b_c|| = 0 contributes 0;
@@ -259,6 +260,30 @@ int64_t apo_select_greedy(const apo_config* c, const double* R) {
   return best;
 }
 
+/* Random rule (I drawn uniformly from the partition). The draws come from
+ * SplitMix64 (G. L. Steele, D. Lea, C. H. Flood, "Fast splittable
+ * pseudorandom number generators", OOPSLA 2014): the generator adds the
+ * constant 0x9e3779b97f4a7c15 to its state at every call and returns the
+ * state through the mixing function below, so output k (from 0) of a
+ * generator seeded with `seed` is mix(seed + (k + 1) * 0x9e37...). */
+uint64_t apo_splitmix64(uint64_t seed, uint64_t k) {
+  uint64_t state = seed + (k + 1) * 0x9e3779b97f4a7c15ULL;
+  state ^= state >> 30;
+  state *= 0xbf58476d1ce4e5b9ULL;
+  state ^= state >> 27;
+  state *= 0x94d049bb133111ebULL;
+  state ^= state >> 31;
+  return state;
+}
+
+/* Block of update u (counted from the start of the solve, over epochs):
+ * floor(h * m / 2^32) with h the high 32 bits of draw u, i.e. h / 2^32 is a
+ * uniform fraction and the block is its share of the m blocks. */
+int64_t apo_select_random(const apo_config* c, uint64_t u) {
+  uint64_t h = apo_splitmix64(c->seed, u) >> 32;
+  return (int64_t)((h * (uint64_t)apo_num_blocks(c)) >> 32);
+}
+
 /* ---- stopping rule (Algorithm 1 test; "Alternating Projection Details") -- */
 
 /* Mean over columns of ||r_c||_2 / ||b_c||_2; a zero column of B counts 0. */
@@ -275,13 +300,18 @@ double apo_rel_residual(const apo_config* c, const double* R, const double* B) {
   return acc / c->l;
 }
 
-/* One epoch: m updates, cyclic (block u at step u) or greedy. If sel_out is
- * not NULL it receives the m selected block indices. */
+/* One epoch: m updates, cyclic (block u at step u), greedy, or random (draw
+ * epoch * m + u at step u; `epoch` counts the epochs before this one). If
+ * sel_out is not NULL it receives the m selected block indices. */
 void apo_epoch(const apo_config* c, const double* X, const double* L, double* W, double* R,
-               int64_t* sel_out) {
+               int64_t epoch, int64_t* sel_out) {
   int64_t m = apo_num_blocks(c);
   for (int64_t u = 0; u < m; ++u) {
-    int64_t blk = (c->order == APO_GREEDY) ? apo_select_greedy(c, R) : u;
+    int64_t blk = u;
+    if (c->order == APO_GREEDY)
+      blk = apo_select_greedy(c, R);
+    else if (c->order == APO_RANDOM)
+      blk = apo_select_random(c, (uint64_t)(epoch * m + u));
     if (sel_out) sel_out[u] = blk;
     apo_update(c, X, L, W, R, blk, NULL);
   }
@@ -309,7 +339,7 @@ int32_t apo_solve(const apo_config* c, const double* X, const double* B, double*
   }
   int32_t status = 1, t = 0;
   while (t < c->max_epochs) {
-    apo_epoch(c, X, L, W, R, NULL);
+    apo_epoch(c, X, L, W, R, t, NULL);
     ++t;
     double rho = apo_rel_residual(c, R, B);
     if (rho_trace) rho_trace[t - 1] = rho;

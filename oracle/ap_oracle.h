@@ -16,7 +16,7 @@ extern "C" {
 #endif
 
 enum { APO_RBF = 0, APO_MATERN32 = 1, APO_MATERN52 = 2 };
-enum { APO_CYCLIC = 0, APO_GREEDY = 1 };
+enum { APO_CYCLIC = 0, APO_GREEDY = 1, APO_RANDOM = 2 };
 
 typedef struct {
   int64_t n;                  /* number of points */
@@ -24,9 +24,10 @@ typedef struct {
   int32_t kernel;             /* APO_RBF, APO_MATERN32, APO_MATERN52 */
   const double* lengthscale;  /* d ARD lengthscales */
   double outputscale, noise;  /* s and sigma^2 */
-  int32_t order;              /* APO_CYCLIC or APO_GREEDY */
+  int32_t order;              /* APO_CYCLIC, APO_GREEDY or APO_RANDOM */
   double tol;                 /* stop when the mean column ratio is < tol */
   int32_t min_epochs, max_epochs;
+  uint64_t seed;              /* APO_RANDOM: seed of the block draws */
 } apo_config;
 
 int32_t apo_num_threads(void);
@@ -48,9 +49,11 @@ void apo_update(const apo_config* c, const double* X, const double* L, double* W
                 int64_t blk, double* delta_out);
 void apo_block_norms(const apo_config* c, const double* R, double* out);
 int64_t apo_select_greedy(const apo_config* c, const double* R);
+uint64_t apo_splitmix64(uint64_t seed, uint64_t k);
+int64_t apo_select_random(const apo_config* c, uint64_t u);
 double apo_rel_residual(const apo_config* c, const double* R, const double* B);
 void apo_epoch(const apo_config* c, const double* X, const double* L, double* W, double* R,
-               int64_t* sel_out);
+               int64_t epoch, int64_t* sel_out);
 int32_t apo_solve(const apo_config* c, const double* X, const double* B, double* W, double* R,
                   double* rho_trace, int32_t* epochs_out);
 void apo_bcd_update(const apo_config* c, const double* X, const double* L, const double* B,

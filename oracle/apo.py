@@ -21,7 +21,7 @@ _SRC = os.path.join(_HERE, "ap_oracle.c")
 _LIB = os.path.join(_HERE, "libaporacle.so")
 
 RBF, MATERN32, MATERN52 = 0, 1, 2
-CYCLIC, GREEDY = 0, 1
+CYCLIC, GREEDY, RANDOM = 0, 1, 2
 KERNELS = {"rbf": RBF, "matern32": MATERN32, "matern52": MATERN52}
 
 
@@ -41,7 +41,8 @@ class _Cfg(ctypes.Structure):
                 ("lengthscale", ctypes.POINTER(ctypes.c_double)),
                 ("outputscale", ctypes.c_double), ("noise", ctypes.c_double),
                 ("order", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("min_epochs", ctypes.c_int32), ("max_epochs", ctypes.c_int32)]
+                ("min_epochs", ctypes.c_int32), ("max_epochs", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
 
 
 _lib = None
@@ -70,8 +71,10 @@ def _load():
             "apo_update": (None, [C, P, P, P, P, I64, P]),
             "apo_block_norms": (None, [C, P, P]),
             "apo_select_greedy": (I64, [C, P]),
+            "apo_splitmix64": (ctypes.c_uint64, [ctypes.c_uint64, ctypes.c_uint64]),
+            "apo_select_random": (I64, [C, ctypes.c_uint64]),
             "apo_rel_residual": (D, [C, P, P]),
-            "apo_epoch": (None, [C, P, P, P, P, P]),
+            "apo_epoch": (None, [C, P, P, P, P, I64, P]),
             "apo_solve": (I32, [C, P, P, P, P, P, P]),
             "apo_bcd_update": (None, [C, P, P, P, P, I64]),
             "apo_residual_rows": (None, [C, P, P, P, P, I64, P]),
@@ -110,6 +113,7 @@ class Problem:
     tol: float = 1e-2
     min_epochs: int = 0
     max_epochs: int = 1000
+    seed: int = 0  # random order: seed of the block draws
     _keep: list = field(default_factory=list, repr=False)
 
     def __post_init__(self):
@@ -141,7 +145,8 @@ class Problem:
         c = _Cfg(self.n, self.d, self.l, self.b, int(self.kernel),
                  self.lengthscale.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                  float(self.outputscale), float(self.noise), int(self.order), float(self.tol),
-                 int(self.min_epochs), int(self.max_epochs))
+                 int(self.min_epochs), int(self.max_epochs),
+                 int(self.seed) & 0xFFFFFFFFFFFFFFFF)
         self._keep = [self.lengthscale]
         return c
 
@@ -265,12 +270,25 @@ def rel_residual(p: Problem, R: np.ndarray, B: np.ndarray | None = None) -> floa
     return float(_load().apo_rel_residual(ctypes.byref(c), _p(_f64(R)), _p(B)))
 
 
-def epoch(p: Problem, L: np.ndarray, W: np.ndarray, R: np.ndarray) -> np.ndarray:
-    """One epoch of m updates in place; returns the selected blocks."""
+def epoch(p: Problem, L: np.ndarray, W: np.ndarray, R: np.ndarray, t: int = 0) -> np.ndarray:
+    """One epoch of m updates in place; returns the selected blocks. t is the
+    number of epochs before this one (the random rule's draws continue
+    across epochs)."""
     sel = np.empty(p.m, dtype=np.int64)
     c = p.cfg()
-    _load().apo_epoch(ctypes.byref(c), _p(p.X), _p(L), _p(W), _p(R), _p(sel))
+    _load().apo_epoch(ctypes.byref(c), _p(p.X), _p(L), _p(W), _p(R), int(t), _p(sel))
     return sel
+
+
+def splitmix64(seed: int, k: int) -> int:
+    """Output k (from 0) of SplitMix64 seeded with `seed`."""
+    return int(_load().apo_splitmix64(int(seed) & 0xFFFFFFFFFFFFFFFF, int(k)))
+
+
+def select_random(p: Problem, u: int) -> int:
+    """The random rule's block for update u since the start of the solve."""
+    c = p.cfg()
+    return int(_load().apo_select_random(ctypes.byref(c), int(u)))
 
 
 @dataclass

@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libapgp.so")
 
 RBF, MATERN32, MATERN52 = 0, 1, 2
-CYCLIC, GREEDY = 0, 1
+CYCLIC, GREEDY, RANDOM = 0, 1, 2
 TILE_FP32, TILE_BF16, TILE_SPLIT, TILE_FP64 = 0, 1, 2, 3
 
 OK, NOT_CONVERGED = 0, 1
@@ -40,7 +40,8 @@ class Config(ctypes.Structure):
                 ("outputscale", ctypes.c_double), ("noise", ctypes.c_double),
                 ("order", ctypes.c_int32), ("tile", ctypes.c_int32),
                 ("refine_every", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("min_epochs", ctypes.c_int32), ("max_epochs", ctypes.c_int32)]
+                ("min_epochs", ctypes.c_int32), ("max_epochs", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
 
 
 class State(ctypes.Structure):
@@ -165,12 +166,13 @@ def _stream(stream=None):
 
 
 def make_config(n, d, l, b, kernel, lengthscale, outputscale=1.0, noise=0.1, order=CYCLIC,
-                tile=TILE_FP32, refine_every=0, tol=1e-2, min_epochs=0, max_epochs=1000):
+                tile=TILE_FP32, refine_every=0, tol=1e-2, min_epochs=0, max_epochs=1000,
+                seed=0):
     ls = np.ascontiguousarray(np.broadcast_to(np.asarray(lengthscale, dtype=np.float64), (d,)))
     cfg = Config(int(n), int(d), int(l), int(b), int(kernel),
                  ls.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(outputscale),
                  float(noise), int(order), int(tile), int(refine_every), float(tol),
-                 int(min_epochs), int(max_epochs))
+                 int(min_epochs), int(max_epochs), int(seed) & 0xFFFFFFFFFFFFFFFF)
     return cfg, ls
 
 
@@ -202,7 +204,7 @@ class Solver:
 
     def __init__(self, X, *, l: int, b: int, kernel: int, lengthscale, outputscale=1.0,
                  noise=0.1, order=CYCLIC, tile=TILE_FP32, refine_every=0, tol=1e-2,
-                 min_epochs=0, max_epochs=1000, stream=None, workspace=None):
+                 min_epochs=0, max_epochs=1000, seed=0, stream=None, workspace=None):
         import torch
         if not (X.is_cuda and X.dtype == torch.float32 and X.dim() == 2 and X.is_contiguous()):
             raise ValueError("X must be a contiguous n x d float32 CUDA tensor")
@@ -211,7 +213,8 @@ class Solver:
         self.n, self.d, self.l, self.b = int(n), int(d), int(l), int(b)
         self.m = (self.n + self.b - 1) // self.b if self.b > 0 else 0
         self.cfg, self._ls = make_config(n, d, l, b, kernel, lengthscale, outputscale, noise,
-                                         order, tile, refine_every, tol, min_epochs, max_epochs)
+                                         order, tile, refine_every, tol, min_epochs, max_epochs,
+                                         seed)
         lib = load()
         need = int(lib.ap_workspace_bytes(ctypes.byref(self.cfg)))
         if need == 0:
@@ -382,7 +385,7 @@ def from_workload(w, device="cuda", tile=TILE_FP32, **over):
     kw = dict(l=w.l, b=w.b, kernel=w.kernel, lengthscale=w.lengthscale,
               outputscale=w.outputscale, noise=w.noise, order=w.order, tile=tile,
               refine_every=w.refine_every, tol=w.tol, min_epochs=w.min_epochs,
-              max_epochs=w.max_epochs)
+              max_epochs=w.max_epochs, seed=w.seed)
     kw.update(over)
     s = Solver(X, **kw)
     W, R = s.new_state(B)

@@ -101,7 +101,8 @@ ap_status check_config(const ap_config* c) {
   if (!c || !c->lengthscale) return AP_ERR_INVALID_ARG;
   if (c->n < 1 || c->d < 1 || c->l < 1 || c->b < 1 || c->b > c->n) return AP_ERR_INVALID_ARG;
   if (c->kernel < AP_RBF || c->kernel > AP_MATERN52) return AP_ERR_INVALID_ARG;
-  if (c->order != AP_CYCLIC && c->order != AP_GREEDY) return AP_ERR_INVALID_ARG;
+  if (c->order != AP_CYCLIC && c->order != AP_GREEDY && c->order != AP_RANDOM)
+    return AP_ERR_INVALID_ARG;
   if (c->tile < AP_TILE_FP32 || c->tile > AP_TILE_FP64) return AP_ERR_INVALID_ARG;
   if (!(c->outputscale > 0.0) || !std::isfinite(c->outputscale)) return AP_ERR_INVALID_ARG;
   if (!(c->noise >= 0.0) || !std::isfinite(c->noise)) return AP_ERR_INVALID_ARG;
@@ -146,8 +147,9 @@ hipError_t mark(ap_problem* h, int phase, hipStream_t s) {
     AP_HIP(mark(h, phase, s));                 \
   } while (0)
 
-// One block update (inner loop of Algorithm 1). block < 0: greedy selection,
-// whose index is already in the control block.
+// One block update (inner loop of Algorithm 1). block < 0: the greedy or
+// random selection, whose index is already in the control block; a random
+// update then draws the next one.
 ap_status one_update(ap_problem* h, const ap_state* st, int32_t block, bool last,
                      hipStream_t s) {
   const bool greedy = h->L.order == AP_GREEDY;
@@ -158,6 +160,8 @@ ap_status one_update(ap_problem* h, const ap_state* st, int32_t block, bool last
   else
     AP_PHASE(kUpdate, ap::launch_fused_update(h->L, h->D, block, st->R, greedy, last, s));
   if (greedy) AP_PHASE(kSelect, ap::launch_select(h->L, h->D, s));
+  if (h->L.order == AP_RANDOM && block < 0)
+    AP_PHASE(kSelect, ap::launch_random_select(h->L, h->D, s));
   return AP_OK;
 }
 
@@ -168,9 +172,9 @@ ap_status refine(ap_problem* h, const ap_state* st, hipStream_t s) {
 }
 
 ap_status enqueue_epoch(ap_problem* h, const ap_state* st, hipStream_t s) {
-  const bool greedy = h->L.order == AP_GREEDY;
+  const bool cyclic = h->L.order == AP_CYCLIC;
   for (int32_t u = 0; u < h->L.m; ++u) {
-    ap_status r = one_update(h, st, greedy ? -1 : u, u == h->L.m - 1, s);
+    ap_status r = one_update(h, st, cyclic ? u : -1, u == h->L.m - 1, s);
     if (r != AP_OK) return r;
   }
   AP_PHASE(kCheck, ap::launch_epoch_check(h->L, h->D, s));
@@ -232,6 +236,7 @@ ap_status ap_factor_blocks(const ap_config* cfg, const float* X, void* ws, size_
   ap::Layout L;
   if (!ap::make_layout(cfg->n, cfg->d, cfg->l, cfg->b, cfg->kernel, cfg->order, cfg->tile, &L))
     return AP_ERR_UNSUPPORTED;
+  L.seed = cfg->seed;
   if (ws_bytes < L.total) return AP_ERR_WORKSPACE;
   ap_problem* h = new (std::nothrow) ap_problem();
   if (!h) {
@@ -552,6 +557,14 @@ ap_status ap_batch_step(const ap_handle* h, const ap_state* st, int32_t count, i
     gsel_a.wg0[k + 1] = gsel_a.wg0[k] + 1;
   }
   gsel_a.count = gsel_n.count;
+  // random order: the next draw of every random problem whose update ran
+  ap::Group grnd{};
+  for (int32_t p = 0; p < count; ++p) {
+    if (h[p]->L.order != AP_RANDOM) continue;
+    const int32_t k = grnd.count++;
+    grnd.desc[k] = h[p]->desc_dev;
+    grnd.wg0[k + 1] = grnd.wg0[k] + 1;
+  }
   // The wide split group and the other tiles run on a second stream beside
   // the narrow group, between a fork after the solves and a join before the
   // epoch advance.
@@ -573,7 +586,7 @@ ap_status ap_batch_step(const ap_handle* h, const ap_state* st, int32_t count, i
       ap_problem* q = h[p];
       if (q->L.tile == AP_TILE_SPLIT) continue;
       const bool greedy = q->L.order == AP_GREEDY;
-      const int code = greedy ? ap::kBlockBatchGreedy : ap::kBlockBatchCyclic;
+      const int code = q->L.order != AP_CYCLIC ? ap::kBlockBatchSel : ap::kBlockBatchCyclic;
       if (q->L.tile == AP_TILE_FP64)
         AP_HIP(ap::launch_fused_update64(q->L, q->D, q->P, q->X, code, st[p].R, greedy, true,
                                          aux->s));
@@ -585,6 +598,7 @@ ap_status ap_batch_step(const ap_handle* h, const ap_state* st, int32_t count, i
       AP_HIP(hipStreamWaitEvent(stream, aux->join, 0));
     }
     if (gsel_n.count > 0) AP_HIP(ap::launch_group_select(gsel_n, gsel_a, stream));
+    if (grnd.count > 0) AP_HIP(ap::launch_group_random(grnd, stream));
     AP_HIP(ap::launch_group_advance(ga, stream));
   }
   return AP_OK;

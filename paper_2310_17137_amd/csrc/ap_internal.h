@@ -24,7 +24,7 @@ constexpr int kMaxD = 20;
 struct Ctl {
   unsigned long long fail;  // first non-positive pivot: (block << 32) | pivot, ~0 if none
   int32_t status;           // 0 ok, else an ap_status (non-finite residual)
-  int32_t sel;              // selected block of the next update (greedy order)
+  int32_t sel;              // selected block of the next update (greedy, random order)
   int32_t epoch;            // epochs completed since the last reset
   int32_t pad0;
   double rho;               // mean column ratio after the last epoch
@@ -39,15 +39,31 @@ struct Ctl {
   int32_t run;              // latched at the end of every batch step from state
   int32_t next_refine;      // > 0: epoch of the next true-residual hold; 0: every refine_every
   double mll_grad[kMaxD + 2];  // last ap_mll_grad: lengthscales, outputscale, noise
+  unsigned long long draws; // random order: block draws made since the last reset
 };
 
 // Block argument of the solve and update launches: >= 0 names the block;
-// kBlockSel takes the greedy selection in ctl->sel; the batch codes take the
-// problem's own cursor (cyclic) or ctl->sel (greedy) and make the launch a
-// no-op while the problem is held.
+// kBlockSel takes the selection in ctl->sel (greedy or random order); the
+// batch codes take the problem's own cursor (cyclic) or ctl->sel and make the
+// launch a no-op while the problem is held.
 constexpr int kBlockSel = -1;
 constexpr int kBlockBatchCyclic = -2;
-constexpr int kBlockBatchGreedy = -3;
+constexpr int kBlockBatchSel = -3;
+
+// Random order (Section 3, "Block Selection": I drawn uniformly from the
+// partition): draw u since the reset takes block floor(h m / 2^32), with h the
+// high 32 bits of output u of SplitMix64 (Steele, Lea and Flood, OOPSLA 2014)
+// started from the seed: z = seed + (u + 1) * 0x9e3779b97f4a7c15, then
+// z ^= z >> 30, z *= 0xbf58476d1ce4e5b9, z ^= z >> 27, z *= 0x94d049bb133111eb,
+// z ^= z >> 31.
+__host__ __device__ inline int32_t random_block(unsigned long long seed, unsigned long long u,
+                                                int32_t m) {
+  unsigned long long z = seed + (u + 1ull) * 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  z ^= z >> 31;
+  return (int32_t)(((z >> 32) * (unsigned long long)m) >> 32);
+}
 
 // Block of this launch, or -1 when a batch step skips a held problem (uniform
 // over the workgroup).
@@ -70,6 +86,7 @@ struct Layout {
   int64_t n, n_pad;      // n_pad >= n + 32, multiple of kRowsWG
   int32_t d, l, b, m, b_pad, last_len;
   int32_t kernel, order, tile;
+  unsigned long long seed;  // random order: seed of the block draws
   int32_t ks;            // BF16 K-steps of 16 feature slots (3d + 6 slots)
   int32_t dp;            // FP32 feature stride (d rounded up to 4)
   int32_t nwg;           // workgroups of the fused update: n_pad / kRowsWG
@@ -174,6 +191,10 @@ hipError_t launch_group_solve(const Group& gp, const Group& gf, hipStream_t st);
 // wide: the group's feature strides are 12 to 20 (else 4 or 8)
 hipError_t launch_group_split(const Group& g, bool wide, hipStream_t st);
 hipError_t launch_group_select(const Group& gn, const Group& ga, hipStream_t st);
+// random order: draw the next block into ctl->sel (grouped: for the problems
+// whose update ran in this batch step)
+hipError_t launch_random_select(const Layout& L, const Dev& D, hipStream_t st);
+hipError_t launch_group_random(const Group& g, hipStream_t st);
 hipError_t launch_group_advance(const Group& g, hipStream_t st);
 hipError_t launch_release(const Dev& D, int32_t next_refine, hipStream_t st);
 

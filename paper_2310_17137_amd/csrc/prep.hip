@@ -136,6 +136,9 @@ __global__ void k_mu_final(Layout L, const double* __restrict__ part, Ctl* ctl) 
     ctl->state = 0;
     ctl->run = 1;
     ctl->next_refine = 0;
+    // random order: the first block is draw 0
+    ctl->draws = L.order == 2 ? 1ull : 0ull;
+    if (L.order == 2) ctl->sel = random_block(L.seed, 0ull, L.m);
   }
 }
 
@@ -276,6 +279,9 @@ __global__ void k_reset_final(Layout L, const double* __restrict__ part, int gro
     ctl->state = 0;
     ctl->run = 1;
     ctl->next_refine = 0;
+    // random order: the first block is draw 0
+    ctl->draws = L.order == 2 ? 1ull : 0ull;
+    if (L.order == 2) ctl->sel = random_block(L.seed, 0ull, L.m);
   }
 }
 
@@ -354,6 +360,27 @@ __global__ __launch_bounds__(256) void g_argmax(Group g) {
   const Desc* ds = g.desc[p];
   const Layout L = ds->L;
   argmax_body(L, ds->D.blocknorm, ds->D.ctl);
+}
+
+// Random order: the block of the next update, draw ctl->draws of the
+// problem's sequence. In a batch step only a problem whose update ran draws,
+// so its sequence does not depend on when it was held.
+__device__ __forceinline__ void random_sel_body(const Layout& L, Ctl* ctl) {
+  if (threadIdx.x == 0) {
+    const unsigned long long u = ctl->draws;
+    ctl->sel = random_block(L.seed, u, L.m);
+    ctl->draws = u + 1ull;
+  }
+}
+
+__global__ void k_random_sel(Layout L, Ctl* ctl) { random_sel_body(L, ctl); }
+
+__global__ void g_random_sel(Group g) {
+  int wg;
+  const int p = group_job(g, &wg);
+  const Desc* ds = g.desc[p];
+  Ctl* ctl = ds->D.ctl;
+  if (ctl->run) random_sel_body(ds->L, ctl);
 }
 
 // Epoch-end check (Section 5, "Alternating Projection Details"): column norms
@@ -477,6 +504,16 @@ hipError_t launch_reset(const Layout& L, const Dev& D, const float* B, double* W
 hipError_t launch_select(const Layout& L, const Dev& D, hipStream_t st) {
   hipLaunchKernelGGL(k_block_norms, dim3(L.m), dim3(256), 0, st, L, D.rowsq, D.blocknorm);
   hipLaunchKernelGGL(k_argmax, dim3(1), dim3(256), 0, st, L, D.blocknorm, D.ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_random_select(const Layout& L, const Dev& D, hipStream_t st) {
+  hipLaunchKernelGGL(k_random_sel, dim3(1), dim3(64), 0, st, L, D.ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_random(const Group& g, hipStream_t st) {
+  hipLaunchKernelGGL(g_random_sel, dim3(g.count), dim3(64), 0, st, g);
   return hipGetLastError();
 }
 

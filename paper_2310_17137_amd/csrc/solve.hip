@@ -141,7 +141,7 @@ __global__ __launch_bounds__(256) void k_bs_finish(Layout L, const Ctl* __restri
 // Grouped forms for a batch step: every workgroup finds its problem in the
 // group and runs the same bodies on that problem's block.
 __device__ __forceinline__ int batch_code(const Layout& L) {
-  return L.order == 1 ? kBlockBatchGreedy : kBlockBatchCyclic;
+  return L.order != 0 ? kBlockBatchSel : kBlockBatchCyclic;
 }
 
 __global__ __launch_bounds__(256) void g_bs_partial(Group g) {

@@ -396,7 +396,7 @@ __global__ __launch_bounds__(256) void g_fused_split(Group g) {
   const Desc* ds = g.desc[p];
   const Layout L = ds->L;
   const int blk =
-      resolve_block(L.order == 1 ? kBlockBatchGreedy : kBlockBatchCyclic, ds->D.ctl);
+      resolve_block(L.order != 0 ? kBlockBatchSel : kBlockBatchCyclic, ds->D.ctl);
   if (blk < 0) return;
   if (L.kernel == 0)
     split_dispatch<0, WIDE>(L, ds, blk, g.R[p], wg, sx);

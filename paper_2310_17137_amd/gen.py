@@ -23,7 +23,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 RBF, MATERN32, MATERN52 = 0, 1, 2
-CYCLIC, GREEDY = 0, 1
+CYCLIC, GREEDY, RANDOM = 0, 1, 2
 KERNEL_NAMES = {RBF: "rbf", MATERN32: "matern32", MATERN52: "matern52"}
 
 
@@ -42,6 +42,7 @@ class Workload:
     min_epochs: int = 0
     max_epochs: int = 1000
     refine_every: int = 0
+    seed: int = 0            # random order: seed of the block draws
     extra: dict = field(default_factory=dict)
 
     @property

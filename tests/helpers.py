@@ -12,7 +12,8 @@ from paper_2310_17137_amd import gen
 def to_oracle(w: gen.Workload, **over) -> apo.Problem:
     kw = dict(X=w.X.astype(np.float64), B=w.B.astype(np.float64), kernel=w.kernel,
               lengthscale=w.lengthscale, outputscale=w.outputscale, noise=w.noise, b=w.b,
-              order=w.order, tol=w.tol, min_epochs=w.min_epochs, max_epochs=w.max_epochs)
+              order=w.order, tol=w.tol, min_epochs=w.min_epochs, max_epochs=w.max_epochs,
+              seed=w.seed)
     kw.update(over)
     return apo.Problem(**kw)
 

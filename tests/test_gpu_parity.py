@@ -215,6 +215,30 @@ def test_epochs_fp64_tiles_match_oracle(case):
         assert abs(rho - rho_o) <= max(1e-5 * rho_o, 1e-7)
 
 
+@pytest.mark.parametrize("case,tile", [(CASES[0], ap.TILE_FP64), (CASES[1], ap.TILE_FP64),
+                                       (CASES[5], ap.TILE_FP64), (CASES[3], ap.TILE_SPLIT)])
+def test_random_order_matches_oracle(case, tile):
+    """Random order (Section 3, "Block Selection"): the device draws each
+    update's block from the seeded generator, the oracle from its own
+    implementation of the same generator; the iterates agree as for cyclic
+    order (a different block anywhere would move W by far more)."""
+    w = _small(case, order=apo.RANDOM)
+    w.seed = 31337 + case[0]
+    s, B, W, R = _gpu(w, tile=tile)
+    s.reset(B, W, R)
+    p = to_oracle(w)
+    L = apo.factor(p)
+    K = dense_khat(p)
+    tol = 1e-5 if tile == ap.TILE_FP64 else max(2 * _epoch_tol(p, L, K), 1e-5)
+    Wo, Ro = np.zeros_like(p.B), p.B.copy()
+    for ep in range(3):
+        s.epoch(B, W, R, 1)
+        apo.epoch(p, L, Wo, Ro, ep)
+        e = _rel(W.cpu().numpy(), Wo)
+        print(f"[random] epoch {ep + 1} W err {e:.3e} (bound {tol:.1e})", flush=True)
+        assert e < tol, ep
+
+
 @pytest.mark.parametrize("l", [32, 1])
 def test_c3_generator_fp64_tiles_track_oracle(l):
     """The ill-conditioned n = 2M recipe at n = 32768 (64-cluster mixture, RBF
@@ -428,7 +452,7 @@ def test_kernel_column_through_unit_blocks(kern, tile):
         R.copy_(torch.from_numpy(Ro.astype(np.float32)).cuda())  # same start for the next column
 
 
-@pytest.mark.parametrize("order", [apo.CYCLIC, apo.GREEDY])
+@pytest.mark.parametrize("order", [apo.CYCLIC, apo.GREEDY, apo.RANDOM])
 def test_graph_replay_equals_eager_launches(order):
     """Epochs replay a captured HIP graph; with profiling on the same launches
     go out one by one. Every replay, with eager work and synchronizations in
