@@ -103,7 +103,7 @@ def workload(name: str):
 
 def describe(w) -> str:
     kern = {0: "rbf", 1: "matern32", 2: "matern52"}[w.kernel]
-    order = "greedy" if w.order == 1 else "cyclic"
+    order = {0: "cyclic", 1: "greedy", 2: "random"}[w.order]
     return (f"{w.name}: n={w.n} d={w.d} l={w.l} b={w.b} m={w.m} kernel={kern} "
             f"noise={w.noise:g} order={order}")
 
@@ -216,6 +216,27 @@ def time_to_tol(w, make, B, tiles):
     return runs
 
 
+def bench_rho_trace(w, make, B, args):
+    """Selection-rule study: the stopping ratio after each of `--rho-trace`
+    epochs on FP64 tiles (whose maintained residual is the true one), for the
+    workload's order and block size."""
+    import torch
+    from paper_2310_17137_amd import ap
+    s, t_factor = make(ap.TILE_FP64)
+    W, R = s.new_state(B)
+    s.reset(B, W, R)
+    rho, t0 = [], time.perf_counter()
+    for e in range(args.rho_trace):
+        s.epoch(B, W, R, 1)
+        rho.append(s.rel_residual()[0])
+        log(f"[rho] epoch {e + 1}: {rho[-1]:.6f} at {time.perf_counter() - t0:.1f} s")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"metric": "stopping ratio per epoch", "workload": describe(w),
+                      "tile": "fp64", "factor_s": t_factor, "epochs": args.rho_trace,
+                      "s_per_epoch": dt / args.rho_trace, "rho": rho}), flush=True)
+
+
 def bench_predict(w, make, args):
     """Posterior mean K(X*, X) W at ns test points from the same generator
     (another seed), W ~ N(0, 1) in FP64 (the rate does not depend on W); the
@@ -324,13 +345,16 @@ def main():
                           "FP64 true-residual refinement and confirmation) and print the time "
                           "to the tolerance instead of the epoch-rate line")
     ap_.add_argument("--b", type=int, default=0, help="override the workload's block size")
-    ap_.add_argument("--order", default="", choices=["", "cyclic", "greedy"],
+    ap_.add_argument("--order", default="", choices=["", "cyclic", "greedy", "random"],
                      help="override the workload's block selection")
     ap_.add_argument("--max-epochs", type=int, default=0,
                      help="with --time-to-tol: epoch limit (0: the workload's)")
     ap_.add_argument("--predict", type=int, default=-1,
                      help="time the posterior mean (ap_predict) at this many test points "
                           "(0: n/4, the paper's 80/20 split) instead of the epoch-rate line")
+    ap_.add_argument("--rho-trace", type=int, default=0,
+                     help="run this many FP64-tile epochs and print the stopping ratio "
+                          "after each (selection-rule study)")
     ap_.add_argument("--mll-grad", action="store_true",
                      help="time the stochastic MLL gradient (ap_mll_grad) instead of the "
                           "epoch-rate line")
@@ -361,7 +385,7 @@ def main():
     if args.b > 0:
         w.b = args.b
     if args.order:
-        w.order = 1 if args.order == "greedy" else 0
+        w.order = {"cyclic": 0, "greedy": 1, "random": 2}[args.order]
     log(f"[bench] generated {describe(w)} in {time.perf_counter() - t:.1f} s")
 
     X = torch.from_numpy(w.X).to(dev)
@@ -376,6 +400,9 @@ def main():
         return
     if args.mll_grad:
         bench_mll_grad(w, make, B, args)
+        return
+    if args.rho_trace > 0:
+        bench_rho_trace(w, make, B, args)
         return
 
     if args.time_to_tol:

@@ -115,6 +115,7 @@ class Server:
             s = ap.Solver(X, l=w.l, b=w.b, kernel=w.kernel, lengthscale=w.lengthscale,
                           outputscale=w.outputscale, noise=w.noise,
                           order=w.order if self.order is None else self.order,
+                          seed=req.rid,  # random order's draws
                           tile=self.tile, refine_every=self.refine_every, tol=self.tol,
                           max_epochs=self.max_epochs, stream=adm)  # factors, syncs `adm`
             W, R = s.new_state(B)
@@ -318,7 +319,7 @@ def main(argv=None):
     p.add_argument("--budget-gb", type=float, default=200.0)
     p.add_argument("--tile", default="split", choices=["split", "fp32", "fp64", "bf16"])
     p.add_argument("--refine-every", type=int, default=5)
-    p.add_argument("--order", default="request", choices=["request", "cyclic", "greedy"],
+    p.add_argument("--order", default="request", choices=["request", "cyclic", "greedy", "random"],
                    help="block selection (request: each request's own)")
     p.add_argument("--steps-per-call", type=int, default=4,
                    help="batch steps enqueued per ap_batch_step call")
@@ -335,7 +336,8 @@ def main(argv=None):
         srv = Server(budget_bytes=a.budget_gb * 1e9, max_active=a.max_active, tile=tile,
                      refine_every=a.refine_every, max_epochs=a.max_epochs,
                      steps_per_call=a.steps_per_call,
-                     order={"request": None, "cyclic": gen.CYCLIC, "greedy": gen.GREEDY}[a.order])
+                     order={"request": None, "cyclic": gen.CYCLIC, "greedy": gen.GREEDY,
+                            "random": gen.RANDOM}[a.order])
         t = time.perf_counter()
         done = srv.run(reqs, log=log)
         out = summarize(done, time.perf_counter() - t)
