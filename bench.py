@@ -237,6 +237,33 @@ def bench_rho_trace(w, make, B, args):
                       "s_per_epoch": dt / args.rho_trace, "rho": rho}), flush=True)
 
 
+def bench_train(w, X, B, args):
+    """Hyperparameter training (Adam, step 0.1, on the stochastic MLL gradient;
+    warm-started solves of `--train-epochs` epochs each): seconds per iteration
+    and the hyperparameter trajectory, starting from the workload's values."""
+    from paper_2310_17137_amd import ap
+    from paper_2310_17137_amd.train import Trainer
+    tile = {v: k for k, v in TILE_NAMES.items()}[args.main]
+    tr = Trainer(X, B, kernel=w.kernel, lengthscale=w.lengthscale, outputscale=w.outputscale,
+                 noise=w.noise, b=w.b, order=w.order, tile=tile, epochs=args.train_epochs)
+    t0 = time.perf_counter()
+    for i in range(args.train):
+        r = tr.step()
+        log(f"[train] step {r.step}: factor {r.t_factor:.2f} s, solve {r.t_solve:.2f} s "
+            f"({r.epochs} epochs, rho {r.rho:.4f}), gradient {r.t_grad:.2f} s; noise "
+            f"{r.theta[-1]:.5f}, outputscale {r.theta[-2]:.4f}")
+    dt = time.perf_counter() - t0
+    h = tr.history
+    print(json.dumps({
+        "metric": "GP training iterations/s", "value": len(h) / dt, "unit": "iterations/s",
+        "workload": describe(w), "tile": args.main, "epochs_per_solve": args.train_epochs,
+        "s_per_iteration": dt / len(h),
+        "phases_s": {"factor": sum(r.t_factor for r in h), "solve": sum(r.t_solve for r in h),
+                     "gradient": sum(r.t_grad for r in h)},
+        "theta_first": h[0].theta.tolist(), "theta_last": h[-1].theta.tolist(),
+        "noise_trajectory": [r.theta[-1] for r in h], "rho": [r.rho for r in h]}), flush=True)
+
+
 def bench_predict(w, make, args):
     """Posterior mean K(X*, X) W at ns test points from the same generator
     (another seed), W ~ N(0, 1) in FP64 (the rate does not depend on W); the
@@ -352,6 +379,10 @@ def main():
     ap_.add_argument("--predict", type=int, default=-1,
                      help="time the posterior mean (ap_predict) at this many test points "
                           "(0: n/4, the paper's 80/20 split) instead of the epoch-rate line")
+    ap_.add_argument("--train", type=int, default=0,
+                     help="run this many hyperparameter-training iterations and time them")
+    ap_.add_argument("--train-epochs", type=int, default=20,
+                     help="epochs of each training iteration's warm-started solve")
     ap_.add_argument("--rho-trace", type=int, default=0,
                      help="run this many FP64-tile epochs and print the stopping ratio "
                           "after each (selection-rule study)")
@@ -403,6 +434,9 @@ def main():
         return
     if args.rho_trace > 0:
         bench_rho_trace(w, make, B, args)
+        return
+    if args.train > 0:
+        bench_train(w, X, B, args)
         return
 
     if args.time_to_tol:

@@ -193,6 +193,17 @@ ap_status ap_rel_residual(ap_handle h, hipStream_t stream, double* rho, double* 
  * AP_NOT_CONVERGED or an error; out [host, may be NULL] gets the statistics. */
 ap_status ap_solve(ap_handle h, const ap_state* st, hipStream_t stream, ap_stats* out);
 
+/* Restart Algorithm 1 from the caller's W instead of W = 0 (a warm start, e.g.
+ * from the solve at the previous hyperparameters of a training loop): the
+ * control block as after ap_reset, W kept, R = B - K^ W as the FP64 true
+ * residual (Lemma residual_equality: Algorithm 1's residual for any W), and
+ * the first selection made from it. Asynchronous. */
+ap_status ap_warm_start(ap_handle h, const ap_state* st, hipStream_t stream);
+
+/* ap_solve from the caller's W: ap_warm_start in place of the reset, then the
+ * same epochs, true residuals and stopping rule. */
+ap_status ap_solve_from(ap_handle h, const ap_state* st, hipStream_t stream, ap_stats* out);
+
 /* True residual B - K^ W over all n^2 kernel entries in FP64 (Lemma
  * residual_equality), written as FP32 to R_out [dev] (NULL: st->R, which
  * refines the maintained residual). col_rel [host, may be NULL] receives the l

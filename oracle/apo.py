@@ -361,3 +361,42 @@ def residual(p: Problem, W: np.ndarray) -> np.ndarray:
     c = p.cfg()
     _load().apo_residual(ctypes.byref(c), _p(p.X), _p(p.B), _p(W), _p(out))
     return out
+
+
+def adam_train(p: Problem, steps: int, epochs: int, lr: float = 0.1, warm: bool = True,
+               beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    """The training loop in FP64 (Section 5, "MLL Optimization": Adam with step
+    size 0.1 on the stochastic gradient of eq. loss_grad_unbiased): per step,
+    the block factors at the current (lengthscales, outputscale, noise), exactly
+    `epochs` epochs of Algorithm 1 from the previous step's W (R = B - K^ W, by
+    Lemma residual_equality) or, without warm, from W = 0, the gradient, and
+    one Adam step (Kingma and Ba, 2015) on the logarithms of the
+    hyperparameters. Returns the hyperparameters and gradients of every step,
+    each a (steps x (d + 2)) array."""
+    import dataclasses
+    d = p.d
+    phi = np.log(np.concatenate([p.lengthscale, [p.outputscale, p.noise]]))
+    m1 = np.zeros_like(phi)
+    m2 = np.zeros_like(phi)
+    W = np.zeros_like(p.B)
+    thetas, grads = [], []
+    for t in range(1, steps + 1):
+        theta = np.exp(phi)
+        q = dataclasses.replace(p, lengthscale=theta[:d].copy(), outputscale=float(theta[d]),
+                                noise=float(theta[d + 1]))
+        L = factor(q)
+        if warm and t > 1:
+            R = residual(q, W)
+        else:
+            W = np.zeros_like(p.B)
+            R = q.B.copy()
+        for e in range(epochs):
+            epoch(q, L, W, R, e)
+        g = mll_grad(q, W)
+        thetas.append(theta)
+        grads.append(g)
+        gphi = g * theta
+        m1 = beta1 * m1 + (1 - beta1) * gphi
+        m2 = beta2 * m2 + (1 - beta2) * gphi ** 2
+        phi = phi - lr * (m1 / (1 - beta1 ** t)) / (np.sqrt(m2 / (1 - beta2 ** t)) + eps)
+    return np.array(thetas), np.array(grads)

@@ -26,7 +26,7 @@ ERR_WORKSPACE, ERR_HIP, ERR_UNSUPPORTED = -4, -5, -6
 
 # every symbol include/ap.h declares
 SYMBOLS = ("ap_workspace_bytes", "ap_factor_blocks", "ap_reset", "ap_epoch", "ap_update",
-           "ap_rel_residual", "ap_solve", "ap_residual", "ap_block_inverse", "ap_set_tile",
+           "ap_rel_residual", "ap_solve", "ap_solve_from", "ap_warm_start", "ap_residual", "ap_block_inverse", "ap_set_tile",
            "ap_profile",
            "ap_profile_read", "ap_predict", "ap_mll_grad", "ap_batch_step", "ap_batch_peek", "ap_batch_release",
            "ap_destroy", "ap_status_str", "ap_last_error")
@@ -122,6 +122,8 @@ def load():
             "ap_update": (I32, [P, S, I32, P]),
             "ap_rel_residual": (I32, [P, P, D, D]),
             "ap_solve": (I32, [P, S, P, St]),
+            "ap_solve_from": (I32, [P, S, P, St]),
+            "ap_warm_start": (I32, [P, S, P]),
             "ap_residual": (I32, [P, S, P, D, P]),
             "ap_block_inverse": (I32, [P, I32, P, P]),
             "ap_predict": (I32, [P, P, P, I64, P, P]),
@@ -260,6 +262,12 @@ class Solver:
         st = self.cstate(B, W, R)
         _check(load().ap_reset(self.handle, ctypes.byref(st), _stream(stream)), "ap_reset")
 
+    def warm_start(self, B, W, R, stream=None):
+        """Restart from the given W: R = B - K^ W (FP64), fresh epoch state."""
+        st = self.cstate(B, W, R)
+        _check(load().ap_warm_start(self.handle, ctypes.byref(st), _stream(stream)),
+               "ap_warm_start")
+
     def epoch(self, B, W, R, epochs: int = 1, stream=None):
         st = self.cstate(B, W, R)
         h = (ctypes.c_void_p * 1)(self.handle.value)
@@ -277,11 +285,13 @@ class Solver:
                "ap_rel_residual")
         return rho.value, np.array(cols[:], dtype=np.float64)
 
-    def solve(self, B, W, R, stream=None) -> SolveStats:
+    def solve(self, B, W, R, warm: bool = False, stream=None) -> SolveStats:
+        """ap_solve (from W = 0), or ap_solve_from (from the given W) if warm."""
         st = self.cstate(B, W, R)
         s = Stats()
-        code = load().ap_solve(self.handle, ctypes.byref(st), _stream(stream), ctypes.byref(s))
-        _check(code, "ap_solve", ok=(OK, NOT_CONVERGED))
+        fn = load().ap_solve_from if warm else load().ap_solve
+        code = fn(self.handle, ctypes.byref(st), _stream(stream), ctypes.byref(s))
+        _check(code, "ap_solve_from" if warm else "ap_solve", ok=(OK, NOT_CONVERGED))
         return SolveStats(code, s.epochs, s.refines, s.rho_maintained, s.rho_true, s.t_epochs,
                           s.t_refine, s.tile, s.escalated_at)
 

@@ -304,7 +304,15 @@ ap_status ap_factor_blocks(const ap_config* cfg, const float* X, void* ws, size_
 ap_status ap_reset(ap_handle h, const ap_state* st, hipStream_t stream) {
   if (!valid_handle(h) || !valid_state(st)) return AP_ERR_INVALID_ARG;
   clear_foreign_error();
-  return hip_fail(ap::launch_reset(h->L, h->D, st->B, st->W, st->R, stream));
+  return hip_fail(ap::launch_reset(h->L, h->D, st->B, st->W, st->R, false, stream));
+}
+
+ap_status ap_warm_start(ap_handle h, const ap_state* st, hipStream_t stream) {
+  if (!valid_handle(h) || !valid_state(st)) return AP_ERR_INVALID_ARG;
+  clear_foreign_error();
+  ap_status r = hip_fail(ap::launch_reset(h->L, h->D, st->B, st->W, st->R, true, stream));
+  if (r != AP_OK) return r;
+  return refine(h, st, stream);
 }
 
 ap_status ap_epoch(const ap_handle* h, const ap_state* st, int32_t count, int32_t epochs,
@@ -362,13 +370,15 @@ ap_status ap_residual(ap_handle h, const ap_state* st, float* R_out, double* col
   return AP_OK;
 }
 
-ap_status ap_solve(ap_handle h, const ap_state* st, hipStream_t stream, ap_stats* out) {
+// ap_solve from W = 0 (warm = false) or from the caller's W (ap_solve_from)
+static ap_status solve_impl(ap_handle h, const ap_state* st, hipStream_t stream, ap_stats* out,
+                            bool warm) {
   if (!valid_handle(h) || !valid_state(st)) return AP_ERR_INVALID_ARG;
   const ap_config& c = h->cfg;
   ap_stats s{};
   s.rho_true = NAN;
   s.escalated_at = -1;
-  ap_status r = ap_reset(h, st, stream);
+  ap_status r = warm ? ap_warm_start(h, st, stream) : ap_reset(h, st, stream);
   if (r != AP_OK) return r;
   ap_status result = AP_NOT_CONVERGED;
   ap::Ctl ctl;
@@ -443,6 +453,14 @@ ap_status ap_solve(ap_handle h, const ap_state* st, hipStream_t stream, ap_stats
   h->L.tile = h->cfg.tile;  // the handle keeps its configured mode
   if (out) *out = s;
   return result;
+}
+
+ap_status ap_solve(ap_handle h, const ap_state* st, hipStream_t stream, ap_stats* out) {
+  return solve_impl(h, st, stream, out, false);
+}
+
+ap_status ap_solve_from(ap_handle h, const ap_state* st, hipStream_t stream, ap_stats* out) {
+  return solve_impl(h, st, stream, out, true);
 }
 
 ap_status ap_set_tile(ap_handle h, int32_t tile) {

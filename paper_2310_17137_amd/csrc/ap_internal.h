@@ -161,8 +161,9 @@ hipError_t launch_prep(const Layout& L, const Dev& D, const Params& P, const flo
                        hipStream_t st);
 hipError_t launch_factor(const Layout& L, const Dev& D, const Params& P, const float* X,
                          hipStream_t st);
+// R = B, the column norms of B, a fresh control block; W = 0 unless keep_w
 hipError_t launch_reset(const Layout& L, const Dev& D, const float* B, double* W, float* R,
-                        hipStream_t st);
+                        bool keep_w, hipStream_t st);
 // block: >= 0, kBlockSel or a batch code (see resolve_block)
 hipError_t launch_block_solve(const Layout& L, const Dev& D, const Params& P, int32_t block,
                               const float* R, double* W, hipStream_t st);

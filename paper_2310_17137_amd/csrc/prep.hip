@@ -233,7 +233,7 @@ __global__ __launch_bounds__(256) void k_prep(Layout L, Params P, const float* _
 __global__ __launch_bounds__(256) void k_reset(Layout L, const float* __restrict__ B,
                                                double* __restrict__ W, float* __restrict__ R,
                                                float* __restrict__ rowsq,
-                                               double* __restrict__ part) {
+                                               double* __restrict__ part, int keep_w) {
   __shared__ double red[256 * 2];
   const int l = L.l;
   double col[kMaxL];
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(256) void k_reset(Layout L, const float* __restrict
       for (int c = 0; c < l; ++c) {
         float v = B[i * l + c];
         R[i * l + c] = v;
-        W[i * l + c] = 0.0;
+        if (!keep_w) W[i * l + c] = 0.0;
         rs = fmaf(v, v, rs);
         col[c] += (double)v * (double)v;
       }
@@ -493,9 +493,10 @@ hipError_t launch_prep(const Layout& L, const Dev& D, const Params& P, const flo
 }
 
 hipError_t launch_reset(const Layout& L, const Dev& D, const float* B, double* W, float* R,
-                        hipStream_t st) {
+                        bool keep_w, hipStream_t st) {
   const int groups = 1024;
-  hipLaunchKernelGGL(k_reset, dim3(groups), dim3(256), 0, st, L, B, W, R, D.rowsq, D.respart);
+  hipLaunchKernelGGL(k_reset, dim3(groups), dim3(256), 0, st, L, B, W, R, D.rowsq, D.respart,
+                     (int)keep_w);
   hipLaunchKernelGGL(k_reset_final, dim3(1), dim3(64), 0, st, L, D.respart, groups, D.ctl);
   if (L.order == 1) return launch_select(L, D, st);
   return hipGetLastError();

@@ -527,3 +527,61 @@ def test_random_order_every_update_decreases_knorm_error():
         assert e <= err * (1 + 1e-12) + 1e-28
         err = e
     assert err < 1e-3 * e0  # 1.1e-4 after 40 epochs on this system (condition number 66)
+
+
+# ---- training loop (Section 5, "MLL Optimization") ---------------------------
+
+
+def _train_problem(n=24, kernel=apo.MATERN52):
+    rng = np.random.default_rng(41)
+    X = rng.uniform(size=(n, 2))
+    y = np.sin(4.0 * X.sum(1)) + 0.1 * rng.standard_normal(n)
+    B = np.concatenate([y[:, None], np.sqrt(n) * np.eye(n)], axis=1)
+    p = apo.Problem(X=X, B=B, kernel=kernel, lengthscale=np.array([0.8, 0.3]), outputscale=0.5,
+                    noise=0.3, b=n)
+    return p, X, y
+
+
+def test_adam_first_step_is_lr_times_sign():
+    """Adam's bias-corrected first step is lr g / (|g| + eps): each log
+    hyperparameter moves by 0.1 against its gradient's sign."""
+    p, _, _ = _train_problem()
+    th, g = apo.adam_train(p, 2, epochs=1)
+    step = np.log(th[1] / th[0])
+    np.testing.assert_allclose(step, -0.1 * np.sign(g[0]), rtol=0, atol=1e-6)
+
+
+def test_adam_training_decreases_exact_negative_mll():
+    """With b = n one epoch is the exact solve, and with the probes
+    sqrt(n) e_i the estimate is the exact gradient (pinned above), so the loop
+    is Adam on the exact negative MLL: 30 steps from a poor start lower it, and
+    the first step's gradient is the finite-difference one."""
+    p, X, y = _train_problem()
+    th, g = apo.adam_train(p, 30, epochs=1)
+    d = 2
+    f = [_neg_mll(X, y, p.kernel, t[:d], t[d], t[d + 1]) for t in th]
+    assert f[-1] < f[0] - 1.0, (f[0], f[-1])
+    h = 1e-6
+    t0 = th[0]
+    fd = np.empty(d + 2)
+    for m in range(d + 2):
+        e = np.zeros(d + 2)
+        e[m] = h
+        a, b = t0 + e, t0 - e
+        fd[m] = (_neg_mll(X, y, p.kernel, a[:d], a[d], a[d + 1])
+                 - _neg_mll(X, y, p.kernel, b[:d], b[d], b[d + 1])) / (2 * h)
+    np.testing.assert_allclose(g[0], fd, rtol=1e-6, atol=1e-6 * np.abs(fd).max())
+
+
+def test_warm_start_continues_algorithm_1():
+    """Lemma residual_equality: restarting Algorithm 1 from any W with
+    R = B - K^ W gives the same iterates as continuing it."""
+    p = _problem(n=320, b=64, l=2, kernel=apo.MATERN32, noise=0.05)
+    L = apo.factor(p)
+    W, R = np.zeros_like(p.B), p.B.copy()
+    apo.epoch(p, L, W, R)
+    W2, R2 = W.copy(), apo.residual(p, W)
+    np.testing.assert_allclose(R2, R, rtol=0, atol=1e-12 * np.abs(p.B).max())
+    apo.epoch(p, L, W, R)
+    apo.epoch(p, L, W2, R2)
+    np.testing.assert_allclose(W2, W, rtol=0, atol=1e-10 * np.abs(W).max())
