@@ -55,7 +55,7 @@ MEASURED_TRAFFIC = {
     ("fp64", "c3"): {
         "bytes": 138812.4 * 1024 * 2.0 + 250001.0 * 1024 * 1.0,
         "files": ("update64.hip", "kmap64.h", "ap_internal.h"),
-        "sha256": "046d24601ac5b81da6bd50d7a81b3417cf835a97fb618142289daa1586a732ce",
+        "sha256": "33d736bdab08eb1b996bc37c859d97f83604c96ae1d2482aba733aa364ae0937",
     },
 }
 
