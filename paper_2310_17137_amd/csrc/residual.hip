@@ -1,9 +1,11 @@
 // FP64 true residual R = B - K^ W over all n^2 kernel entries (Lemma
 // residual_equality: the maintained residual equals this in exact arithmetic,
 // so recomputing it removes the drift of the reduced-precision update).
-// Exact differencing of the FP32 inputs widened to FP64, FP64 kernel map, FP64
-// accumulation in a fixed column order on the FP64 matrix cores. The columns'
-// features and weights are staged through LDS.
+// The FP32 inputs are widened to FP64 and scaled by 1 / ell (as in the FP64-tile
+// update), then differenced in FP64; FP64 kernel map, FP64 accumulation in a
+// fixed column order on the FP64 matrix cores, and the noise term added per row
+// after the column loop. The columns' features and weights are staged through
+// LDS.
 #include <algorithm>
 
 #include "ap_internal.h"
@@ -12,20 +14,21 @@
 namespace ap {
 namespace {
 
-constexpr int kCols = 64;  // columns staged in LDS per step
-constexpr int kResWG = 128; // rows per workgroup: 4 waves x two 16-row tiles
+constexpr int kCols = 64;   // columns staged in LDS per step
+constexpr int kResWG = 256; // rows per workgroup: 4 waves x four 16-row tiles
 
 typedef __attribute__((ext_vector_type(4))) double f64x4;
 
-// The product sum_j K^_ij W_jc runs on v_mfma_f64_16x16x4f64: per step of 4
+// The product sum_j K_ij W_jc runs on v_mfma_f64_16x16x4f64: per step of 4
 // columns a lane evaluates one kernel entry per row tile (row lane % 16, column
 // lane / 16) in FP64 on the vector ALUs, and the matrix cores accumulate
 // acc[c][i] += W^T[c][j] K^T[j][i] for 16 right-hand sides per half (NH halves).
+// The noise term sigma^2 W_i of K^ W is added per row after the column loop.
 //
 // With PRED the rows are nr test points Xr instead of the training points: the
 // kernel computes the posterior mean K(Xr, X) W (no noise term, Section 2 GP
 // regression) into mean (nr x l, FP64) and skips the norms.
-template <int KERN, int DP, int NH, bool PRED>
+template <int KERN, int DV, int DP, int NH, bool PRED>
 __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const float* __restrict__ X,
                                                   const float* __restrict__ Xr, int64_t nr,
                                                   const float* __restrict__ B,
@@ -42,19 +45,20 @@ __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const floa
   const int d = L.d, l = L.l;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int ln = lane % 16, lg = lane / 16;
-  const int64_t row0 = (int64_t)blockIdx.x * kResWG + wave * 32;
-  double inv_ell[DP], xi[2][DP];
+  const int64_t row0 = (int64_t)blockIdx.x * kResWG + wave * 64;
+  double inv_ell[DV], xi[4][DV];
 #pragma unroll
-  for (int k = 0; k < DP; ++k) inv_ell[k] = k < d ? 1.0 / P.ell[k] : 0.0;
+  for (int k = 0; k < DV; ++k) inv_ell[k] = k < d ? 1.0 / P.ell[k] : 0.0;
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < 4; ++t) {
     const int64_t i = row0 + 16 * t + ln;
 #pragma unroll
-    for (int k = 0; k < DP; ++k) xi[t][k] = (i < nr && k < d) ? (double)Xr[i * d + k] : 0.0;
+    for (int k = 0; k < DV; ++k)
+      xi[t][k] = (i < nr && k < d) ? (double)Xr[i * d + k] * inv_ell[k] : 0.0;
   }
-  f64x4 acc[2][NH];
+  f64x4 acc[4][NH];
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+  for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int h = 0; h < NH; ++h) acc[t][h] = f64x4{0.0, 0.0, 0.0, 0.0};
 
@@ -62,29 +66,29 @@ __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const floa
     __syncthreads();
     for (int e = threadIdx.x; e < kCols * DP; e += 256) {
       const int jj = e / DP, k = e % DP;
-      sx[jj][k] = (j0 + jj < L.n && k < d) ? (double)X[(j0 + jj) * d + k] : 0.0;
+      sx[jj][k] = (j0 + jj < L.n && k < d) ? (double)X[(j0 + jj) * d + k] * (1.0 / P.ell[k])
+                                            : 0.0;
     }
     for (int e = threadIdx.x; e < kCols * 16 * NH; e += 256) {
       const int jj = e / (16 * NH), c = e % (16 * NH);
       sw[jj][c] = (j0 + jj < L.n && c < l) ? W[(j0 + jj) * l + c] : 0.0;
     }
     __syncthreads();
+#pragma unroll 1
     for (int st = 0; st < kCols / 4; ++st) {
       const int jj = 4 * st + lg;
-      const int64_t j = j0 + jj;
       double a[NH];
 #pragma unroll
       for (int h = 0; h < NH; ++h) a[h] = sw[jj][16 * h + ln];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
+      for (int t = 0; t < 4; ++t) {
         double r2 = 0.0;
 #pragma unroll
-        for (int k = 0; k < DP; ++k) {
-          const double df = (xi[t][k] - sx[jj][k]) * inv_ell[k];
+        for (int k = 0; k < DV; ++k) {
+          const double df = xi[t][k] - sx[jj][k];
           r2 = fma(df, df, r2);
         }
-        double kv = kernel_fp64<KERN>(r2, etab);
-        if (!PRED && j == row0 + 16 * t + ln) kv += P.noise;
+        const double kv = kernel_fp64<KERN>(r2, etab);
 #pragma unroll
         for (int h = 0; h < NH; ++h)
           acc[t][h] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[h], kv, acc[t][h], 0, 0, 0);
@@ -95,7 +99,7 @@ __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const floa
   // c = 16 h + lane / 16 + 4 q (the FP64 16x16 accumulator layout)
   if constexpr (PRED) {
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < 4; ++t) {
       const int64_t i = row0 + 16 * t + ln;
 #pragma unroll
       for (int h = 0; h < NH; ++h)
@@ -113,7 +117,7 @@ __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const floa
 #pragma unroll
     for (int q = 0; q < 4; ++q) csum[h][q] = 0.0;
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < 4; ++t) {
     const int64_t i = row0 + 16 * t + ln;
     const bool live = i < nr;
     double rs = 0.0;
@@ -123,7 +127,8 @@ __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const floa
       for (int q = 0; q < 4; ++q) {
         const int c = 16 * h + lg + 4 * q;
         if (live && c < l) {
-          const double r = (double)B[i * l + c] - acc[t][h][q];
+          const double kw = fma(P.noise, W[i * l + c], acc[t][h][q]);
+          const double r = (double)B[i * l + c] - kw;
           Rout[i * l + c] = (float)r;
           rs = fma(r, r, rs);
           csum[h][q] = fma(r, r, csum[h][q]);
@@ -157,8 +162,8 @@ __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const floa
 // fused update does for l <= 8: an FP64 FMA and an FP64 matrix instruction
 // retire multiply-adds at the same rate on gfx950, and the matrix tile would
 // pad l to 16). Each lane accumulates the columns j = 4 st + lane / 16 of its
-// two rows; the four lanes of a row add their partials in a fixed order.
-template <int KERN, int DP, int NV, bool PRED>
+// four rows; the four lanes of a row add their partials in a fixed order.
+template <int KERN, int DV, int DP, int NV, bool PRED>
 __global__ __launch_bounds__(256) void k_residualv(Layout L, Params P, const float* __restrict__ X,
                                                    const float* __restrict__ Xr, int64_t nr,
                                                    const float* __restrict__ B,
@@ -176,19 +181,20 @@ __global__ __launch_bounds__(256) void k_residualv(Layout L, Params P, const flo
   const int d = L.d, l = L.l;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int ln = lane % 16, lg = lane / 16;
-  const int64_t row0 = (int64_t)blockIdx.x * kResWG + wave * 32;
-  double inv_ell[DP], xi[2][DP];
+  const int64_t row0 = (int64_t)blockIdx.x * kResWG + wave * 64;
+  double inv_ell[DV], xi[4][DV];
 #pragma unroll
-  for (int k = 0; k < DP; ++k) inv_ell[k] = k < d ? 1.0 / P.ell[k] : 0.0;
+  for (int k = 0; k < DV; ++k) inv_ell[k] = k < d ? 1.0 / P.ell[k] : 0.0;
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < 4; ++t) {
     const int64_t i = row0 + 16 * t + ln;
 #pragma unroll
-    for (int k = 0; k < DP; ++k) xi[t][k] = (i < nr && k < d) ? (double)Xr[i * d + k] : 0.0;
+    for (int k = 0; k < DV; ++k)
+      xi[t][k] = (i < nr && k < d) ? (double)Xr[i * d + k] * inv_ell[k] : 0.0;
   }
-  double acc[2][NV];
+  double acc[4][NV];
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+  for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int c = 0; c < NV; ++c) acc[t][c] = 0.0;
 
@@ -196,36 +202,36 @@ __global__ __launch_bounds__(256) void k_residualv(Layout L, Params P, const flo
     __syncthreads();
     for (int e = threadIdx.x; e < kCols * DP; e += 256) {
       const int jj = e / DP, k = e % DP;
-      sx[jj][k] = (j0 + jj < L.n && k < d) ? (double)X[(j0 + jj) * d + k] : 0.0;
+      sx[jj][k] = (j0 + jj < L.n && k < d) ? (double)X[(j0 + jj) * d + k] * (1.0 / P.ell[k])
+                                            : 0.0;
     }
     for (int e = threadIdx.x; e < kCols * NV; e += 256) {
       const int jj = e / NV, c = e % NV;
       sw[jj][c] = (j0 + jj < L.n && c < l) ? W[(j0 + jj) * l + c] : 0.0;
     }
     __syncthreads();
+#pragma unroll 1
     for (int st = 0; st < kCols / 4; ++st) {
       const int jj = 4 * st + lg;
-      const int64_t j = j0 + jj;
       double a[NV];
 #pragma unroll
       for (int c = 0; c < NV; ++c) a[c] = sw[jj][c];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
+      for (int t = 0; t < 4; ++t) {
         double r2 = 0.0;
 #pragma unroll
-        for (int k = 0; k < DP; ++k) {
-          const double df = (xi[t][k] - sx[jj][k]) * inv_ell[k];
+        for (int k = 0; k < DV; ++k) {
+          const double df = xi[t][k] - sx[jj][k];
           r2 = fma(df, df, r2);
         }
-        double kv = kernel_fp64<KERN>(r2, etab);
-        if (!PRED && j == row0 + 16 * t + ln) kv += P.noise;
+        const double kv = kernel_fp64<KERN>(r2, etab);
 #pragma unroll
         for (int c = 0; c < NV; ++c) acc[t][c] = fma(kv, a[c], acc[t][c]);
       }
     }
   }
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+  for (int t = 0; t < 4; ++t)
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
       acc[t][c] += __shfl_xor(acc[t][c], 16);
@@ -233,7 +239,7 @@ __global__ __launch_bounds__(256) void k_residualv(Layout L, Params P, const flo
     }
   if constexpr (PRED) {
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
+    for (int t = 0; t < 4; ++t) {
       const int64_t i = row0 + 16 * t + ln;
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
@@ -251,7 +257,7 @@ __global__ __launch_bounds__(256) void k_residualv(Layout L, Params P, const flo
 #pragma unroll
   for (int q = 0; q < NQ; ++q) csum[q] = 0.0;
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < 4; ++t) {
     const int64_t i = row0 + 16 * t + ln;
     const bool live = i < nr;
     double rs = 0.0;
@@ -263,7 +269,8 @@ __global__ __launch_bounds__(256) void k_residualv(Layout L, Params P, const flo
       for (int cc = 4 * q; cc < 4 * q + 4 && cc < NV; ++cc)
         if (cc == c) v = acc[t][cc];
       if (live && c < l) {
-        const double r = (double)B[i * l + c] - v;
+        const double kw = fma(P.noise, W[i * l + c], v);
+        const double r = (double)B[i * l + c] - kw;
         Rout[i * l + c] = (float)r;
         rs = fma(r, r, rs);
         csum[q] = fma(r, r, csum[q]);
@@ -322,7 +329,7 @@ __global__ __launch_bounds__(256) void k_residual_final(Layout L, const double* 
 }
 
 // Rows: nr points Xr (the training points for the residual, test points for
-// the posterior mean); 128 rows per workgroup.
+// the posterior mean); 256 rows per workgroup.
 struct ResArgs {
   const float* X;
   const float* Xr;
@@ -338,15 +345,19 @@ struct ResArgs {
 template <int KERN, int NH, bool PRED>
 void launch_res_d(const Layout& L, const Params& P, const ResArgs& a, hipStream_t st) {
   const dim3 g((unsigned)((a.nr + kResWG - 1) / kResWG)), t(256);
-#define AP_RES(DP)                                                                           \
-  hipLaunchKernelGGL((k_residual<KERN, DP, NH, PRED>), g, t, 0, st, L, P, a.X, a.Xr, a.nr, a.B, \
-                     a.W, a.Rout, a.mean, a.rowsq, a.part)
-  switch (L.dp) {
-    case 4: AP_RES(4); break;
-    case 8: AP_RES(8); break;
-    case 12: AP_RES(12); break;
-    case 16: AP_RES(16); break;
-    default: AP_RES(20); break;
+#define AP_RES(DV, DP)                                                                       \
+  hipLaunchKernelGGL((k_residual<KERN, DV, DP, NH, PRED>), g, t, 0, st, L, P, a.X, a.Xr, a.nr, \
+                     a.B, a.W, a.Rout, a.mean, a.rowsq, a.part)
+  if (L.d == 3) {
+    AP_RES(3, 4);
+  } else {
+    switch (L.dp) {
+      case 4: AP_RES(4, 4); break;
+      case 8: AP_RES(8, 8); break;
+      case 12: AP_RES(12, 12); break;
+      case 16: AP_RES(16, 16); break;
+      default: AP_RES(20, 20); break;
+    }
   }
 #undef AP_RES
 }
@@ -354,15 +365,19 @@ void launch_res_d(const Layout& L, const Params& P, const ResArgs& a, hipStream_
 template <int KERN, int NV, bool PRED>
 void launch_res_v(const Layout& L, const Params& P, const ResArgs& a, hipStream_t st) {
   const dim3 g((unsigned)((a.nr + kResWG - 1) / kResWG)), t(256);
-#define AP_RESV(DP)                                                                          \
-  hipLaunchKernelGGL((k_residualv<KERN, DP, NV, PRED>), g, t, 0, st, L, P, a.X, a.Xr, a.nr, a.B, \
-                     a.W, a.Rout, a.mean, a.rowsq, a.part)
-  switch (L.dp) {
-    case 4: AP_RESV(4); break;
-    case 8: AP_RESV(8); break;
-    case 12: AP_RESV(12); break;
-    case 16: AP_RESV(16); break;
-    default: AP_RESV(20); break;
+#define AP_RESV(DV, DP)                                                                      \
+  hipLaunchKernelGGL((k_residualv<KERN, DV, DP, NV, PRED>), g, t, 0, st, L, P, a.X, a.Xr, a.nr, \
+                     a.B, a.W, a.Rout, a.mean, a.rowsq, a.part)
+  if (L.d == 3) {
+    AP_RESV(3, 4);
+  } else {
+    switch (L.dp) {
+      case 4: AP_RESV(4, 4); break;
+      case 8: AP_RESV(8, 8); break;
+      case 12: AP_RESV(12, 12); break;
+      case 16: AP_RESV(16, 16); break;
+      default: AP_RESV(20, 20); break;
+    }
   }
 #undef AP_RESV
 }
