@@ -7,8 +7,9 @@
 // Each block lives in a b_pad x b_pad row-major slot (b_pad = b rounded up to
 // 64). Rows and columns past the block's length hold the identity, so every
 // slot is factored the same way and its inverse is [[A^{-1}, 0], [0, I]].
-// The work is split in 64 x 64 FP64 tiles staged through LDS; each launch
-// covers one tile step for all m blocks at once:
+// The work is split in 64 x 64 FP64 tiles staged through LDS, their products on
+// the FP64 matrix cores; each launch covers one tile step for all m blocks at
+// once:
 //   Cholesky  (right-looking):  diag factor + diag inverse, panel solve, trailing update
 //   L^{-1}    (column blocks from the right, through a panel buffer)
 //   L^{-T}L^{-1} (block rows from the top, in place), then mirror to the upper half.
@@ -37,46 +38,78 @@ __device__ inline double kernel_fp64(int kern, const float* __restrict__ xi,
   return P.s * (1.0 + t + (5.0 / 3.0) * r2) * exp(-t);
 }
 
-__device__ inline void load_tile(double* s, const double* __restrict__ g, int ld, bool trans) {
-  for (int e = threadIdx.x; e < kT * kT; e += blockDim.x) {
-    int r = e / kT, c = e % kT;
-    double v = g[(size_t)r * ld + c];
-    if (trans) s[c * LDT + r] = v; else s[r * LDT + c] = v;
+// A 64 x 64 tile moves global -> registers -> LDS: each of the 256 threads
+// loads 16 elements, all issued before the first is stored.
+constexpr int kPerThread = kT * kT / 256;
+
+__device__ inline void fetch_tile(double v[kPerThread], const double* __restrict__ g, int ld) {
+#pragma unroll
+  for (int u = 0; u < kPerThread; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    v[u] = g[(size_t)(e / kT) * ld + e % kT];
   }
 }
 
-// acc (4x4 per thread) += sA (64x64) * sB (64x64); thread t owns rows
-// 4(t/16)..+3 and columns 4(t%16)..+3 of the product.
-__device__ inline void mma_tile(const double* sA, const double* sB, double acc[4][4]) {
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+__device__ inline void put_tile(double* s, const double v[kPerThread], bool trans, int lds) {
+#pragma unroll
+  for (int u = 0; u < kPerThread; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    const int r = e / kT, c = e % kT;
+    if (trans) s[c * lds + r] = v[u]; else s[r * lds + c] = v[u];
+  }
+}
+
+__device__ inline void load_tile(double* s, const double* __restrict__ g, int ld, bool trans,
+                                 int lds) {
+  double v[kPerThread];
+  fetch_tile(v, g, ld);
+  put_tile(s, v, trans, lds);
+}
+
+// 64 x 64 x 64 tile products on the FP64 matrix cores (v_mfma_f64_16x16x4f64).
+// Wave w computes rows 16 w .. 16 w + 15 of the product as four 16 x 16
+// accumulators; lane holds C[16 w + lane / 16 + 4 q][16 ct + lane % 16] in
+// acc[ct][q]. A tiles (the left operand) are staged with row stride LDA, B
+// tiles with LDB: 4 and 16 mod 32 doubles, so that the 64 lanes' operand reads
+// spread over the LDS banks.
+constexpr int LDA = kT + 4;
+constexpr int LDB = kT + 16;
+typedef __attribute__((ext_vector_type(4))) double f64x4;
+
+__device__ inline void mma_tile(const double* sA, const double* sB, f64x4 acc[4]) {
+  const int lane = threadIdx.x % 64, w = threadIdx.x / 64;
+  const int ln = lane % 16, lg = lane / 16;
+  const double* a_row = sA + (16 * w + ln) * LDA + lg;  // A[m = lane % 16][k = lane / 16]
 #pragma unroll 4
-  for (int k = 0; k < kT; ++k) {
-    double a[4], b[4];
+  for (int s = 0; s < kT / 4; ++s) {
+    const double a = a_row[4 * s];
+    const double* b_row = sB + (4 * s + lg) * LDB + ln;  // B[k = lane / 16][n = lane % 16]
 #pragma unroll
-    for (int r = 0; r < 4; ++r) a[r] = sA[(ty * 4 + r) * LDT + k];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) b[c] = sB[k * LDT + tx * 4 + c];
-#pragma unroll
-    for (int r = 0; r < 4; ++r)
-#pragma unroll
-      for (int c = 0; c < 4; ++c) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+    for (int ct = 0; ct < 4; ++ct)
+      acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b_row[16 * ct], acc[ct], 0, 0, 0);
   }
 }
 
-__device__ inline void zero_acc(double acc[4][4]) {
+__device__ inline void zero_acc(f64x4 acc[4]) {
 #pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+  for (int ct = 0; ct < 4; ++ct) acc[ct] = f64x4{0.0, 0.0, 0.0, 0.0};
 }
 
-__device__ inline void store_acc(double* __restrict__ g, int ld, const double acc[4][4],
+// element (row, col) of the 64 x 64 product this lane holds as acc[ct][q]
+#define AP_ACC_FOR(BODY)                                   \
+  do {                                                     \
+    const int lane_ = threadIdx.x % 64, w_ = threadIdx.x / 64; \
+    _Pragma("unroll") for (int ct = 0; ct < 4; ++ct)       \
+      _Pragma("unroll") for (int q = 0; q < 4; ++q) {      \
+        const int row = 16 * w_ + lane_ / 16 + 4 * q;      \
+        const int col = 16 * ct + lane_ % 16;              \
+        BODY;                                              \
+      }                                                    \
+  } while (0)
+
+__device__ inline void store_acc(double* __restrict__ g, int ld, const f64x4 acc[4],
                                  double scale) {
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-#pragma unroll
-  for (int r = 0; r < 4; ++r)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) g[(size_t)(ty * 4 + r) * ld + tx * 4 + c] = scale * acc[r][c];
+  AP_ACC_FOR(g[(size_t)row * ld + col] = scale * acc[ct][q]);
 }
 
 __device__ inline double* slot(const Layout& L, double* base, int64_t j) {
@@ -128,7 +161,7 @@ __global__ __launch_bounds__(256) void k_potrf_diag(Layout L, double* __restrict
   __shared__ double x[kT * LDT];
   const int64_t j = blockIdx.x;
   double* G = tile(L, slot(L, A, j), k, k);
-  load_tile(s, G, L.b_pad, false);
+  load_tile(s, G, L.b_pad, false, LDT);
   __syncthreads();
   const int t = threadIdx.x;
   for (int kk = 0; kk < kT; ++kk) {
@@ -173,17 +206,17 @@ __global__ __launch_bounds__(256) void k_potrf_diag(Layout L, double* __restrict
 // L_ik = A_ik L_kk^{-T} for the tiles i > k of column k.
 __global__ __launch_bounds__(256) void k_trsm(Layout L, double* __restrict__ A,
                                               const double* __restrict__ dinv, int k) {
-  __shared__ double sA[kT * LDT];
-  __shared__ double sB[kT * LDT];
+  __shared__ double sA[kT * LDA];
+  __shared__ double sB[kT * LDB];
   const int nt = L.b_pad / kT;
   const int rows = nt - k - 1;
   const int64_t j = blockIdx.x / rows;
   const int i = k + 1 + (int)(blockIdx.x % rows);
   double* G = tile(L, slot(L, A, j), i, k);
-  load_tile(sA, G, L.b_pad, false);
-  load_tile(sB, scratch_tile(L, const_cast<double*>(dinv), j, k), kT, true);
+  load_tile(sA, G, L.b_pad, false, LDA);
+  load_tile(sB, scratch_tile(L, const_cast<double*>(dinv), j, k), kT, true, LDB);
   __syncthreads();
-  double acc[4][4];
+  f64x4 acc[4];
   zero_acc(acc);
   mma_tile(sA, sB, acc);
   store_acc(G, L.b_pad, acc, 1.0);
@@ -191,8 +224,8 @@ __global__ __launch_bounds__(256) void k_trsm(Layout L, double* __restrict__ A,
 
 // A_ij -= L_ik L_jk^T for k < j <= i.
 __global__ __launch_bounds__(256) void k_syrk(Layout L, double* __restrict__ A, int k) {
-  __shared__ double sA[kT * LDT];
-  __shared__ double sB[kT * LDT];
+  __shared__ double sA[kT * LDA];
+  __shared__ double sB[kT * LDB];
   const int nt = L.b_pad / kT;
   const int r = nt - k - 1;
   const int64_t tiles = (int64_t)r * (r + 1) / 2;
@@ -202,21 +235,17 @@ __global__ __launch_bounds__(256) void k_syrk(Layout L, double* __restrict__ A, 
   while (t > ii) { t -= ii + 1; ++ii; }
   const int i = k + 1 + ii, jj = k + 1 + (int)t;
   double* Aj = slot(L, A, j);
-  load_tile(sA, tile(L, Aj, i, k), L.b_pad, false);
-  load_tile(sB, tile(L, Aj, jj, k), L.b_pad, true);
+  load_tile(sA, tile(L, Aj, i, k), L.b_pad, false, LDA);
+  load_tile(sB, tile(L, Aj, jj, k), L.b_pad, true, LDB);
+  double* G = tile(L, Aj, i, jj);
+  // the target's elements in the accumulator layout, fetched before the products
+  double old[4][4];
+  AP_ACC_FOR(old[ct][q] = G[(size_t)row * L.b_pad + col]);
   __syncthreads();
-  double acc[4][4];
+  f64x4 acc[4];
   zero_acc(acc);
   mma_tile(sA, sB, acc);
-  double* G = tile(L, Aj, i, jj);
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      size_t o = (size_t)(ty * 4 + a) * L.b_pad + tx * 4 + c;
-      G[o] = G[o] - acc[a][c];
-    }
+  AP_ACC_FOR(G[(size_t)row * L.b_pad + col] = old[ct][q] - acc[ct][q]);
 }
 
 // ---- L^{-1}: column block j, tiles i > j:  X_ij = -(sum_{k=j+1..i} X_ik L_kj) X_jj
@@ -224,31 +253,36 @@ __global__ __launch_bounds__(256) void k_syrk(Layout L, double* __restrict__ A, 
 __global__ __launch_bounds__(256) void k_trtri_panel(Layout L, const double* __restrict__ A,
                                                      const double* __restrict__ dinv,
                                                      double* __restrict__ panel, int jc) {
-  __shared__ double sA[kT * LDT];
-  __shared__ double sB[kT * LDT];
+  __shared__ double sA[kT * LDA];
+  __shared__ double sB[kT * LDB];
   const int nt = L.b_pad / kT;
   const int rows = nt - jc - 1;
   const int64_t j = blockIdx.x / rows;
   const int i = jc + 1 + (int)(blockIdx.x % rows);
   const double* Aj = slot(L, const_cast<double*>(A), j);
-  double acc[4][4];
+  f64x4 acc[4];
   zero_acc(acc);
+  // the next step's tiles are fetched into registers while this step's
+  // products run
+  double va[kPerThread], vb[kPerThread];
+  fetch_tile(va, tile(L, const_cast<double*>(Aj), i, jc + 1), L.b_pad);
+  fetch_tile(vb, tile(L, const_cast<double*>(Aj), jc + 1, jc), L.b_pad);
   for (int k = jc + 1; k <= i; ++k) {
-    load_tile(sA, tile(L, const_cast<double*>(Aj), i, k), L.b_pad, false);
-    load_tile(sB, tile(L, const_cast<double*>(Aj), k, jc), L.b_pad, false);
+    put_tile(sA, va, false, LDA);
+    put_tile(sB, vb, false, LDB);
     __syncthreads();
+    if (k < i) {
+      fetch_tile(va, tile(L, const_cast<double*>(Aj), i, k + 1), L.b_pad);
+      fetch_tile(vb, tile(L, const_cast<double*>(Aj), k + 1, jc), L.b_pad);
+    }
     mma_tile(sA, sB, acc);
     __syncthreads();
   }
   // sA <- T, sB <- X_jj
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int c = 0; c < 4; ++c) sA[(ty * 4 + a) * LDT + tx * 4 + c] = acc[a][c];
-  load_tile(sB, scratch_tile(L, const_cast<double*>(dinv), j, jc), kT, false);
+  AP_ACC_FOR(sA[row * LDA + col] = acc[ct][q]);
+  load_tile(sB, scratch_tile(L, const_cast<double*>(dinv), j, jc), kT, false, LDB);
   __syncthreads();
-  double acc2[4][4];
+  f64x4 acc2[4];
   zero_acc(acc2);
   mma_tile(sA, sB, acc2);
   store_acc(scratch_tile(L, panel, j, i), kT, acc2, -1.0);
@@ -273,19 +307,26 @@ __global__ __launch_bounds__(256) void k_trtri_writeback(Layout L, double* __res
 // ---- L^{-T} L^{-1} in place, block row i: tile (i, jc) = sum_{k>=i} X_ki^T X_kjc
 __global__ __launch_bounds__(256) void k_lauum(Layout L, double* __restrict__ A, int i,
                                                int diag) {
-  __shared__ double sA[kT * LDT];
-  __shared__ double sB[kT * LDT];
+  __shared__ double sA[kT * LDA];
+  __shared__ double sB[kT * LDB];
   const int nt = L.b_pad / kT;
   const int cols = diag ? 1 : i;
   const int64_t j = blockIdx.x / cols;
   const int jc = diag ? i : (int)(blockIdx.x % cols);
   double* Aj = slot(L, A, j);
-  double acc[4][4];
+  f64x4 acc[4];
   zero_acc(acc);
+  double va[kPerThread], vb[kPerThread];
+  fetch_tile(va, tile(L, Aj, i, i), L.b_pad);
+  fetch_tile(vb, tile(L, Aj, i, jc), L.b_pad);
   for (int k = i; k < nt; ++k) {
-    load_tile(sA, tile(L, Aj, k, i), L.b_pad, true);
-    load_tile(sB, tile(L, Aj, k, jc), L.b_pad, false);
+    put_tile(sA, va, true, LDA);
+    put_tile(sB, vb, false, LDB);
     __syncthreads();
+    if (k + 1 < nt) {
+      fetch_tile(va, tile(L, Aj, k + 1, i), L.b_pad);
+      fetch_tile(vb, tile(L, Aj, k + 1, jc), L.b_pad);
+    }
     mma_tile(sA, sB, acc);
     __syncthreads();
   }
