@@ -239,6 +239,22 @@ def test_random_order_matches_oracle(case, tile):
         assert e < tol, ep
 
 
+def test_random_order_single_block_equals_cyclic():
+    """m = 1: every draw is block 0, so random order is cyclic order bit for bit."""
+    case = CASES[4]  # b = n
+    wr = _small(case, order=apo.RANDOM)
+    wr.seed = 99
+    wc = _small(case)
+    sr, B, Wr, Rr = _gpu(wr, tile=ap.TILE_FP64)
+    sc, _, Wc, Rc = _gpu(wc, tile=ap.TILE_FP64)
+    sr.reset(B, Wr, Rr)
+    sc.reset(B, Wc, Rc)
+    sr.epoch(B, Wr, Rr, 3)
+    sc.epoch(B, Wc, Rc, 3)
+    torch.cuda.synchronize()
+    assert torch.equal(Wr, Wc) and torch.equal(Rr, Rc)
+
+
 @pytest.mark.parametrize("l", [32, 1])
 def test_c3_generator_fp64_tiles_track_oracle(l):
     """The ill-conditioned n = 2M recipe at n = 32768 (64-cluster mixture, RBF
