@@ -28,9 +28,9 @@
  *    nothing aborts or exits. Out-parameters are left untouched on error unless
  *    stated otherwise.
  *  - Work is enqueued on the given HIP stream in stream order. Only
- *    ap_factor_blocks, ap_solve, ap_rel_residual and ap_residual with a non-NULL
- *    col_rel synchronize that stream (ap_batch_peek synchronizes a stream of
- *    its own). A handle is used by one host thread at a
+ *    ap_factor_blocks, ap_solve, ap_solve_from, ap_mll_grad, ap_rel_residual
+ *    and ap_residual with a non-NULL col_rel synchronize that stream
+ *    (ap_batch_peek synchronizes a stream of its own). A handle is used by one host thread at a
  *    time, and calls that overlap on one handle race, except ap_batch_peek,
  *    which only reads and may watch a call running on another thread.
  *  - Errors the device detects (a non-positive pivot, a non-finite residual)
@@ -154,7 +154,7 @@ ap_status ap_factor_blocks(const ap_config* cfg, const float* X, void* ws, size_
                            hipStream_t stream, ap_handle* out, int64_t* bad_block);
 
 /* Algorithm 1 initialization: W = 0, R = B; also caches ||B_c|| and, for the
- * greedy order, the first selection. Asynchronous. */
+ * greedy and random orders, makes the first selection. Asynchronous. */
 ap_status ap_reset(ap_handle h, const ap_state* st, hipStream_t stream);
 
 /* Run `epochs` epochs of m block updates on each of `count` problems (h[i],
@@ -221,8 +221,8 @@ ap_status ap_residual(ap_handle h, const ap_state* st, float* R_out, double* col
  * storing any of them.
  *  grad     [host] d + 2 values: d/d ell_1 .. d/d ell_d, d/ds, d/d sigma^2.
  *  partials [dev, may be NULL] ceil(n/64) x 22 FP64: the same sums over each
- *           64-row slice of the double sum (columns d + 2 .. 21 zero), whose
- *           sum in row order is grad.
+ *           64-row slice of the double sum (columns d + 2 .. 21 zero), which
+ *           add up to grad (summed by the library in a fixed order).
  * Synchronizes the stream. AP_ERR_NONFINITE if a component is not finite. */
 ap_status ap_mll_grad(ap_handle h, const ap_state* st, double* grad, double* partials,
                       hipStream_t stream);
