@@ -239,6 +239,29 @@ def test_random_order_matches_oracle(case, tile):
         assert e < tol, ep
 
 
+@pytest.mark.parametrize("n,d,l,b,kern,order", [
+    (8500, 3, 4, 4096, apo.RBF, apo.GREEDY),     # the largest block (m = 3, last block 308)
+    (900, 20, 20, 256, apo.MATERN32, apo.CYCLIC),  # the most features, matrix-core product
+])
+def test_limits_fp64_tiles_match_oracle(n, d, l, b, kern, order):
+    """The build's size limits (b = 4096, d = 20) on FP64 tiles: two epochs
+    against the oracle's iterates, as for the small cases."""
+    rng = np.random.default_rng(n + d)
+    w = gen.small(12, n, d, l, b, kernel=kern, noise=0.05,
+                  ell=(0.3 if d == 3 else 2.0) * rng.uniform(0.8, 1.25, size=d), order=order)
+    s, B, W, R = _gpu(w, tile=ap.TILE_FP64)
+    s.reset(B, W, R)
+    p = to_oracle(w)
+    L = apo.factor(p)
+    Wo, Ro = np.zeros_like(p.B), p.B.copy()
+    for ep in range(2):
+        s.epoch(B, W, R, 1)
+        apo.epoch(p, L, Wo, Ro, ep)
+        e = _rel(W.cpu().numpy(), Wo)
+        print(f"[limits] n={n} d={d} b={b} epoch {ep + 1}: W err {e:.3e}", flush=True)
+        assert e < 1e-5, ep
+
+
 def test_random_order_single_block_equals_cyclic():
     """m = 1: every draw is block 0, so random order is cyclic order bit for bit."""
     case = CASES[4]  # b = n
