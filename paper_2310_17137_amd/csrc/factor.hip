@@ -10,7 +10,8 @@
 // The work is split in 64 x 64 FP64 tiles staged through LDS, their products on
 // the FP64 matrix cores; each launch covers one tile step for all m blocks at
 // once:
-//   Cholesky  (right-looking):  diag factor + diag inverse, panel solve, trailing update
+//   Cholesky  (left-looking):  update of the tile column by the earlier panels,
+//             diag factor + diag inverse, panel solve
 //   L^{-1}    (column blocks from the right, through a panel buffer)
 //   L^{-T}L^{-1} (block rows from the top, in place), then mirror to the upper half.
 #include <algorithm>
@@ -222,30 +223,39 @@ __global__ __launch_bounds__(256) void k_trsm(Layout L, double* __restrict__ A,
   store_acc(G, L.b_pad, acc, 1.0);
 }
 
-// A_ij -= L_ik L_jk^T for k < j <= i.
-__global__ __launch_bounds__(256) void k_syrk(Layout L, double* __restrict__ A, int k) {
+// Left-looking update of tile column k before its factorization:
+// A_ik -= sum_{p<k} L_ip L_kp^T for the tiles i >= k, the sum accumulated in
+// registers over the earlier panels (tiles prefetched one step ahead), so each
+// target tile is read and written once.
+__global__ __launch_bounds__(256) void k_herk(Layout L, double* __restrict__ A, int k) {
   __shared__ double sA[kT * LDA];
   __shared__ double sB[kT * LDB];
   const int nt = L.b_pad / kT;
-  const int r = nt - k - 1;
-  const int64_t tiles = (int64_t)r * (r + 1) / 2;
-  const int64_t j = blockIdx.x / tiles;
-  int64_t t = blockIdx.x % tiles;
-  int ii = 0;
-  while (t > ii) { t -= ii + 1; ++ii; }
-  const int i = k + 1 + ii, jj = k + 1 + (int)t;
+  const int rows = nt - k;
+  const int64_t j = blockIdx.x / rows;
+  const int i = k + (int)(blockIdx.x % rows);
   double* Aj = slot(L, A, j);
-  load_tile(sA, tile(L, Aj, i, k), L.b_pad, false, LDA);
-  load_tile(sB, tile(L, Aj, jj, k), L.b_pad, true, LDB);
-  double* G = tile(L, Aj, i, jj);
-  // the target's elements in the accumulator layout, fetched before the products
-  double old[4][4];
-  AP_ACC_FOR(old[ct][q] = G[(size_t)row * L.b_pad + col]);
-  __syncthreads();
   f64x4 acc[4];
   zero_acc(acc);
-  mma_tile(sA, sB, acc);
-  AP_ACC_FOR(G[(size_t)row * L.b_pad + col] = old[ct][q] - acc[ct][q]);
+  double va[kPerThread], vb[kPerThread];
+  fetch_tile(va, tile(L, Aj, i, 0), L.b_pad);
+  fetch_tile(vb, tile(L, Aj, k, 0), L.b_pad);
+  for (int p = 0; p < k; ++p) {
+    put_tile(sA, va, false, LDA);
+    put_tile(sB, vb, true, LDB);
+    __syncthreads();
+    if (p + 1 < k) {
+      fetch_tile(va, tile(L, Aj, i, p + 1), L.b_pad);
+      fetch_tile(vb, tile(L, Aj, k, p + 1), L.b_pad);
+    }
+    mma_tile(sA, sB, acc);
+    __syncthreads();
+  }
+  double* G = tile(L, Aj, i, k);
+  AP_ACC_FOR({
+    const size_t o = (size_t)row * L.b_pad + col;
+    G[o] = G[o] - acc[ct][q];
+  });
 }
 
 // ---- L^{-1}: column block j, tiles i > j:  X_ij = -(sum_{k=j+1..i} X_ik L_kj) X_jj
@@ -372,15 +382,14 @@ hipError_t launch_factor(const Layout& L, const Dev& D, const Params& P, const f
   const int64_t tri = (int64_t)nt * (nt + 1) / 2;
   hipLaunchKernelGGL(k_form, dim3((unsigned)(m * tri)), dim3(256), 0, st, L, P, X, D.kinv);
   for (int k = 0; k < nt; ++k) {
+    if (k > 0)
+      hipLaunchKernelGGL(k_herk, dim3((unsigned)(m * (nt - k))), dim3(256), 0, st, L, D.kinv, k);
     hipLaunchKernelGGL(k_potrf_diag, dim3((unsigned)m), dim3(256), 0, st, L, D.kinv, D.dinv,
                        D.ctl, k);
     const int r = nt - k - 1;
-    if (r > 0) {
+    if (r > 0)
       hipLaunchKernelGGL(k_trsm, dim3((unsigned)(m * r)), dim3(256), 0, st, L, D.kinv, D.dinv,
                          k);
-      hipLaunchKernelGGL(k_syrk, dim3((unsigned)(m * r * (r + 1) / 2)), dim3(256), 0, st, L,
-                         D.kinv, k);
-    }
   }
   for (int jc = nt - 1; jc >= 0; --jc) {
     const int rows = nt - jc - 1;
