@@ -113,6 +113,17 @@ __device__ inline void store_acc(double* __restrict__ g, int ld, const f64x4 acc
   AP_ACC_FOR(g[(size_t)row * ld + col] = scale * acc[ct][q]);
 }
 
+// XCD-aware workgroup order: the dispatcher deals consecutive workgroups to
+// the 8 XCDs in turn, so the workgroups of one block (which stream the same
+// panel tiles) would be spread over all 8 L2 caches. Renumbered, XCD x runs a
+// contiguous range of logical indices (a bijection of 0 .. gridDim.x - 1).
+__device__ inline int64_t xcd_order() {
+  const int64_t nwg = gridDim.x, b = blockIdx.x;
+  const int64_t per = nwg / 8, rem = nwg % 8;
+  const int64_t x = b % 8, r = b / 8;
+  return x * per + (x < rem ? x : rem) + r;
+}
+
 __device__ inline double* slot(const Layout& L, double* base, int64_t j) {
   return base + (size_t)j * L.b_pad * L.b_pad;
 }
@@ -211,8 +222,9 @@ __global__ __launch_bounds__(256) void k_trsm(Layout L, double* __restrict__ A,
   __shared__ double sB[kT * LDB];
   const int nt = L.b_pad / kT;
   const int rows = nt - k - 1;
-  const int64_t j = blockIdx.x / rows;
-  const int i = k + 1 + (int)(blockIdx.x % rows);
+  const int64_t wg = xcd_order();
+  const int64_t j = wg / rows;
+  const int i = k + 1 + (int)(wg % rows);
   double* G = tile(L, slot(L, A, j), i, k);
   load_tile(sA, G, L.b_pad, false, LDA);
   load_tile(sB, scratch_tile(L, const_cast<double*>(dinv), j, k), kT, true, LDB);
@@ -232,8 +244,9 @@ __global__ __launch_bounds__(256) void k_herk(Layout L, double* __restrict__ A, 
   __shared__ double sB[kT * LDB];
   const int nt = L.b_pad / kT;
   const int rows = nt - k;
-  const int64_t j = blockIdx.x / rows;
-  const int i = k + (int)(blockIdx.x % rows);
+  const int64_t wg = xcd_order();
+  const int64_t j = wg / rows;
+  const int i = k + (int)(wg % rows);
   double* Aj = slot(L, A, j);
   f64x4 acc[4];
   zero_acc(acc);
@@ -267,8 +280,9 @@ __global__ __launch_bounds__(256) void k_trtri_panel(Layout L, const double* __r
   __shared__ double sB[kT * LDB];
   const int nt = L.b_pad / kT;
   const int rows = nt - jc - 1;
-  const int64_t j = blockIdx.x / rows;
-  const int i = jc + 1 + (int)(blockIdx.x % rows);
+  const int64_t wg = xcd_order();
+  const int64_t j = wg / rows;
+  const int i = jc + 1 + (int)(wg % rows);
   const double* Aj = slot(L, const_cast<double*>(A), j);
   f64x4 acc[4];
   zero_acc(acc);
@@ -321,8 +335,9 @@ __global__ __launch_bounds__(256) void k_lauum(Layout L, double* __restrict__ A,
   __shared__ double sB[kT * LDB];
   const int nt = L.b_pad / kT;
   const int cols = diag ? 1 : i;
-  const int64_t j = blockIdx.x / cols;
-  const int jc = diag ? i : (int)(blockIdx.x % cols);
+  const int64_t wg = xcd_order();
+  const int64_t j = wg / cols;
+  const int jc = diag ? i : (int)(wg % cols);
   double* Aj = slot(L, A, j);
   f64x4 acc[4];
   zero_acc(acc);
