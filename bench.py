@@ -264,6 +264,40 @@ def bench_train(w, X, B, args):
         "noise_trajectory": [r.theta[-1] for r in h], "rho": [r.rho for r in h]}), flush=True)
 
 
+def bench_rmse(w, make, B, args):
+    """Test-time solve and held-out error: solve K^ W = y (the workload's
+    targets alone) to the stopping rule on FP64 tiles, then the posterior mean
+    at held-out points of the same mixture and its RMSE against their noisy
+    targets (the target noise has sd 0.01)."""
+    import torch
+    from paper_2310_17137_amd import ap, gen
+    if not w.name.startswith("c3") or w.l != 1:
+        raise SystemExit("--rmse runs on the n = 2M inputs with y alone (--workload c3-l1)")
+    s, t_factor = make(ap.TILE_FP64)
+    W, R = s.new_state(B)
+    t0 = time.perf_counter()
+    st = s.solve(B, W, R)
+    t_solve = time.perf_counter() - t0
+    log(f"[rmse] solve: {st.epochs} epochs, rho_true {st.rho_true:.5f}, {t_solve:.2f} s")
+    Xt_h, yt = gen.c3_heldout(n_test=args.rmse)
+    Xt = torch.from_numpy(Xt_h).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mean = s.predict(W, Xt)
+    torch.cuda.synchronize()
+    t_pred = time.perf_counter() - t0
+    err = mean.cpu().numpy()[:, 0] - yt
+    rmse = float(np.sqrt(np.mean(err ** 2)))
+    print(json.dumps({
+        "metric": "held-out RMSE after the test-time solve", "value": rmse, "unit": "RMSE",
+        "higher_is_better": False, "workload": describe(w), "tile": "fp64",
+        "test_points": int(args.rmse), "target_noise_sd": 0.01,
+        "rmse_of_zero_prediction": float(np.sqrt(np.mean(yt ** 2))),
+        "solve": {"converged": st.converged, "epochs": st.epochs, "rho_true": st.rho_true,
+                  "factor_s": t_factor, "solve_s": t_solve},
+        "predict_s": t_pred}), flush=True)
+
+
 def bench_predict(w, make, args):
     """Posterior mean K(X*, X) W at ns test points from the same generator
     (another seed), W ~ N(0, 1) in FP64 (the rate does not depend on W); the
@@ -379,6 +413,9 @@ def main():
     ap_.add_argument("--predict", type=int, default=-1,
                      help="time the posterior mean (ap_predict) at this many test points "
                           "(0: n/4, the paper's 80/20 split) instead of the epoch-rate line")
+    ap_.add_argument("--rmse", type=int, default=0,
+                     help="test-time solve of y, then the posterior mean's RMSE at this many "
+                          "held-out points (--workload c3-l1)")
     ap_.add_argument("--train", type=int, default=0,
                      help="run this many hyperparameter-training iterations and time them")
     ap_.add_argument("--train-epochs", type=int, default=20,
@@ -437,6 +474,9 @@ def main():
         return
     if args.train > 0:
         bench_train(w, X, B, args)
+        return
+    if args.rmse > 0:
+        bench_rmse(w, make, B, args)
         return
 
     if args.time_to_tol:

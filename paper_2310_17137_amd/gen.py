@@ -122,6 +122,24 @@ def c3(seed: int = 0, n: int = 2_000_000, l: int = 32, b: int = 2048,
                     b=b, tol=1e-2, refine_every=5)
 
 
+def c3_heldout(seed: int = 0, n_test: int = 100_000):
+    """Held-out points of the c3(seed) mixture: the same 64 centres (that
+    generator's first draw), new points and target noise from a stream of
+    their own; returns (X_test as float32, y_test as float64) with
+    y = sin(2 pi sum x) + N(0, 0.01^2), as for the training targets."""
+    d = 3
+    centres = np.random.default_rng(seed).uniform(0.0, 1.0, size=(64, d))
+    rng = np.random.default_rng([seed, 7])
+    comp = rng.integers(0, 64, size=n_test)
+    X = centres[comp] + 0.02 * rng.standard_normal((n_test, d))
+    bad = np.nonzero(((X < 0.0) | (X > 1.0)).any(1))[0]
+    while bad.size:
+        X[bad] = centres[comp[bad]] + 0.02 * rng.standard_normal((bad.size, d))
+        bad = bad[((X[bad] < 0.0) | (X[bad] > 1.0)).any(1)]
+    y = np.sin(2 * np.pi * X.sum(1)) + 0.01 * rng.standard_normal(n_test)
+    return X.astype(np.float32), y
+
+
 def c4(seed: int = 0, n: int = 4_000_000, l: int = 8, b: int = 2048) -> Workload:
     """Gas-sensors scale: n = 4 000 000, d = 11, 95% draws U[-1,1]^11 plus 5%
     exact copies of uniformly chosen draws, shuffled; Matern-3/2 ARD with
