@@ -15,7 +15,11 @@ namespace ap {
 namespace {
 
 constexpr int kCols = 64;   // columns staged in LDS per step
-constexpr int kResWG = 256; // rows per workgroup: 4 waves x four 16-row tiles
+
+// Row tiles (16 rows) per wave: a workgroup covers 64 TL rows. Large n takes
+// four (the staged columns serve more rows); small n one, so that enough
+// workgroups exist to fill the chip.
+inline int res_tiles(int64_t nr) { return nr >= (int64_t(1) << 20) ? 4 : (nr >= (1 << 17) ? 2 : 1); }
 
 typedef __attribute__((ext_vector_type(4))) double f64x4;
 
@@ -28,7 +32,7 @@ typedef __attribute__((ext_vector_type(4))) double f64x4;
 // With PRED the rows are nr test points Xr instead of the training points: the
 // kernel computes the posterior mean K(Xr, X) W (no noise term, Section 2 GP
 // regression) into mean (nr x l, FP64) and skips the norms.
-template <int KERN, int DV, int DP, int NH, bool PRED>
+template <int KERN, int DV, int DP, int NH, int TL, bool PRED>
 __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const float* __restrict__ X,
                                                   const float* __restrict__ Xr, int64_t nr,
                                                   const float* __restrict__ B,
@@ -45,20 +49,20 @@ __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const floa
   const int d = L.d, l = L.l;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int ln = lane % 16, lg = lane / 16;
-  const int64_t row0 = (int64_t)blockIdx.x * kResWG + wave * 64;
-  double inv_ell[DV], xi[4][DV];
+  const int64_t row0 = (int64_t)blockIdx.x * (64 * TL) + wave * (16 * TL);
+  double inv_ell[DV], xi[TL][DV];
 #pragma unroll
   for (int k = 0; k < DV; ++k) inv_ell[k] = k < d ? 1.0 / P.ell[k] : 0.0;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < TL; ++t) {
     const int64_t i = row0 + 16 * t + ln;
 #pragma unroll
     for (int k = 0; k < DV; ++k)
       xi[t][k] = (i < nr && k < d) ? (double)Xr[i * d + k] * inv_ell[k] : 0.0;
   }
-  f64x4 acc[4][NH];
+  f64x4 acc[TL][NH];
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < TL; ++t)
 #pragma unroll
     for (int h = 0; h < NH; ++h) acc[t][h] = f64x4{0.0, 0.0, 0.0, 0.0};
 
@@ -81,7 +85,7 @@ __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const floa
 #pragma unroll
       for (int h = 0; h < NH; ++h) a[h] = sw[jj][16 * h + ln];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < TL; ++t) {
         double r2 = 0.0;
 #pragma unroll
         for (int k = 0; k < DV; ++k) {
@@ -99,7 +103,7 @@ __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const floa
   // c = 16 h + lane / 16 + 4 q (the FP64 16x16 accumulator layout)
   if constexpr (PRED) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < TL; ++t) {
       const int64_t i = row0 + 16 * t + ln;
 #pragma unroll
       for (int h = 0; h < NH; ++h)
@@ -117,7 +121,7 @@ __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const floa
 #pragma unroll
     for (int q = 0; q < 4; ++q) csum[h][q] = 0.0;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < TL; ++t) {
     const int64_t i = row0 + 16 * t + ln;
     const bool live = i < nr;
     double rs = 0.0;
@@ -163,7 +167,7 @@ __global__ __launch_bounds__(256) void k_residual(Layout L, Params P, const floa
 // retire multiply-adds at the same rate on gfx950, and the matrix tile would
 // pad l to 16). Each lane accumulates the columns j = 4 st + lane / 16 of its
 // four rows; the four lanes of a row add their partials in a fixed order.
-template <int KERN, int DV, int DP, int NV, bool PRED>
+template <int KERN, int DV, int DP, int NV, int TL, bool PRED>
 __global__ __launch_bounds__(256) void k_residualv(Layout L, Params P, const float* __restrict__ X,
                                                    const float* __restrict__ Xr, int64_t nr,
                                                    const float* __restrict__ B,
@@ -181,20 +185,20 @@ __global__ __launch_bounds__(256) void k_residualv(Layout L, Params P, const flo
   const int d = L.d, l = L.l;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int ln = lane % 16, lg = lane / 16;
-  const int64_t row0 = (int64_t)blockIdx.x * kResWG + wave * 64;
-  double inv_ell[DV], xi[4][DV];
+  const int64_t row0 = (int64_t)blockIdx.x * (64 * TL) + wave * (16 * TL);
+  double inv_ell[DV], xi[TL][DV];
 #pragma unroll
   for (int k = 0; k < DV; ++k) inv_ell[k] = k < d ? 1.0 / P.ell[k] : 0.0;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < TL; ++t) {
     const int64_t i = row0 + 16 * t + ln;
 #pragma unroll
     for (int k = 0; k < DV; ++k)
       xi[t][k] = (i < nr && k < d) ? (double)Xr[i * d + k] * inv_ell[k] : 0.0;
   }
-  double acc[4][NV];
+  double acc[TL][NV];
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < TL; ++t)
 #pragma unroll
     for (int c = 0; c < NV; ++c) acc[t][c] = 0.0;
 
@@ -217,7 +221,7 @@ __global__ __launch_bounds__(256) void k_residualv(Layout L, Params P, const flo
 #pragma unroll
       for (int c = 0; c < NV; ++c) a[c] = sw[jj][c];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < TL; ++t) {
         double r2 = 0.0;
 #pragma unroll
         for (int k = 0; k < DV; ++k) {
@@ -231,7 +235,7 @@ __global__ __launch_bounds__(256) void k_residualv(Layout L, Params P, const flo
     }
   }
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < TL; ++t)
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
       acc[t][c] += __shfl_xor(acc[t][c], 16);
@@ -239,7 +243,7 @@ __global__ __launch_bounds__(256) void k_residualv(Layout L, Params P, const flo
     }
   if constexpr (PRED) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < TL; ++t) {
       const int64_t i = row0 + 16 * t + ln;
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
@@ -257,7 +261,7 @@ __global__ __launch_bounds__(256) void k_residualv(Layout L, Params P, const flo
 #pragma unroll
   for (int q = 0; q < NQ; ++q) csum[q] = 0.0;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < TL; ++t) {
     const int64_t i = row0 + 16 * t + ln;
     const bool live = i < nr;
     double rs = 0.0;
@@ -299,12 +303,12 @@ __global__ __launch_bounds__(256) void k_residualv(Layout L, Params P, const flo
 }
 
 __global__ __launch_bounds__(256) void k_residual_final(Layout L, const double* __restrict__ part,
-                                                        Ctl* ctl) {
+                                                        int groups, Ctl* ctl) {
   __shared__ double red[256];
   __shared__ double ratio[kMaxL];
   for (int c = 0; c < L.l; ++c) {
     double acc = 0.0;
-    for (int g = threadIdx.x; g < L.nwg_res; g += 256) acc += part[(size_t)g * kMaxL + c];
+    for (int g = threadIdx.x; g < groups; g += 256) acc += part[(size_t)g * kMaxL + c];
     red[threadIdx.x] = acc;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
@@ -329,7 +333,7 @@ __global__ __launch_bounds__(256) void k_residual_final(Layout L, const double* 
 }
 
 // Rows: nr points Xr (the training points for the residual, test points for
-// the posterior mean); 256 rows per workgroup.
+// the posterior mean); 64 res_tiles(nr) rows per workgroup.
 struct ResArgs {
   const float* X;
   const float* Xr;
@@ -342,12 +346,12 @@ struct ResArgs {
   double* part;
 };
 
-template <int KERN, int NH, bool PRED>
+template <int KERN, int NH, int TL, bool PRED>
 void launch_res_d(const Layout& L, const Params& P, const ResArgs& a, hipStream_t st) {
-  const dim3 g((unsigned)((a.nr + kResWG - 1) / kResWG)), t(256);
+  const dim3 g((unsigned)((a.nr + 64 * TL - 1) / (64 * TL))), t(256);
 #define AP_RES(DV, DP)                                                                       \
-  hipLaunchKernelGGL((k_residual<KERN, DV, DP, NH, PRED>), g, t, 0, st, L, P, a.X, a.Xr, a.nr, \
-                     a.B, a.W, a.Rout, a.mean, a.rowsq, a.part)
+  hipLaunchKernelGGL((k_residual<KERN, DV, DP, NH, TL, PRED>), g, t, 0, st, L, P, a.X, a.Xr,  \
+                     a.nr, a.B, a.W, a.Rout, a.mean, a.rowsq, a.part)
   if (L.d == 3) {
     AP_RES(3, 4);
   } else {
@@ -362,12 +366,12 @@ void launch_res_d(const Layout& L, const Params& P, const ResArgs& a, hipStream_
 #undef AP_RES
 }
 
-template <int KERN, int NV, bool PRED>
+template <int KERN, int NV, int TL, bool PRED>
 void launch_res_v(const Layout& L, const Params& P, const ResArgs& a, hipStream_t st) {
-  const dim3 g((unsigned)((a.nr + kResWG - 1) / kResWG)), t(256);
+  const dim3 g((unsigned)((a.nr + 64 * TL - 1) / (64 * TL))), t(256);
 #define AP_RESV(DV, DP)                                                                      \
-  hipLaunchKernelGGL((k_residualv<KERN, DV, DP, NV, PRED>), g, t, 0, st, L, P, a.X, a.Xr, a.nr, \
-                     a.B, a.W, a.Rout, a.mean, a.rowsq, a.part)
+  hipLaunchKernelGGL((k_residualv<KERN, DV, DP, NV, TL, PRED>), g, t, 0, st, L, P, a.X, a.Xr, \
+                     a.nr, a.B, a.W, a.Rout, a.mean, a.rowsq, a.part)
   if (L.d == 3) {
     AP_RESV(3, 4);
   } else {
@@ -382,20 +386,29 @@ void launch_res_v(const Layout& L, const Params& P, const ResArgs& a, hipStream_
 #undef AP_RESV
 }
 
+template <int KERN, int TL, bool PRED>
+void launch_res_t(const Layout& L, const Params& P, const ResArgs& a, hipStream_t st) {
+  if (L.l <= 1)
+    launch_res_v<KERN, 1, TL, PRED>(L, P, a, st);
+  else if (L.l <= 2)
+    launch_res_v<KERN, 2, TL, PRED>(L, P, a, st);
+  else if (L.l <= 4)
+    launch_res_v<KERN, 4, TL, PRED>(L, P, a, st);
+  else if (L.l <= 8)
+    launch_res_v<KERN, 8, TL, PRED>(L, P, a, st);
+  else if (L.l <= 16)
+    launch_res_d<KERN, 1, TL, PRED>(L, P, a, st);
+  else
+    launch_res_d<KERN, 2, TL, PRED>(L, P, a, st);
+}
+
 template <int KERN, bool PRED>
 void launch_res_k(const Layout& L, const Params& P, const ResArgs& a, hipStream_t st) {
-  if (L.l <= 1)
-    launch_res_v<KERN, 1, PRED>(L, P, a, st);
-  else if (L.l <= 2)
-    launch_res_v<KERN, 2, PRED>(L, P, a, st);
-  else if (L.l <= 4)
-    launch_res_v<KERN, 4, PRED>(L, P, a, st);
-  else if (L.l <= 8)
-    launch_res_v<KERN, 8, PRED>(L, P, a, st);
-  else if (L.l <= 16)
-    launch_res_d<KERN, 1, PRED>(L, P, a, st);
-  else
-    launch_res_d<KERN, 2, PRED>(L, P, a, st);
+  switch (res_tiles(a.nr)) {
+    case 4: launch_res_t<KERN, 4, PRED>(L, P, a, st); break;
+    case 2: launch_res_t<KERN, 2, PRED>(L, P, a, st); break;
+    default: launch_res_t<KERN, 1, PRED>(L, P, a, st); break;
+  }
 }
 
 template <bool PRED>
@@ -415,7 +428,9 @@ hipError_t launch_residual(const Layout& L, const Dev& D, const Params& P, const
   // refining in place keeps the greedy rule's row norms in step with R
   const ResArgs a{X, X, L.n, B, W, Rout, nullptr, in_place ? D.rowsq : nullptr, D.respart};
   launch_res<false>(L, P, a, st);
-  hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(256), 0, st, L, D.respart, D.ctl);
+  const int tl = res_tiles(L.n);
+  const int groups = (int)((L.n + 64 * tl - 1) / (64 * tl));
+  hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(256), 0, st, L, D.respart, groups, D.ctl);
   return hipGetLastError();
 }
 
