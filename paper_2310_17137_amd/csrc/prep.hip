@@ -30,7 +30,7 @@ bool make_layout(int64_t n, int32_t d, int32_t l, int32_t b, int32_t kernel, int
   o.n_pad = (n + 32 + kRowsWG - 1) / kRowsWG * kRowsWG;
   o.nwg = (int32_t)(o.n_pad / kRowsWG);
   // the true residual's per-workgroup partials: at most one per 64 rows (its
-  // workgroups cover 64, 128 or 256 rows by n)
+  // workgroups cover 64 or 256 rows by n)
   o.nwg_res = (int32_t)((n + 63) / 64);
   size_t off = 0;
   auto take = [&](size_t bytes) {

@@ -16,10 +16,10 @@ namespace {
 
 constexpr int kCols = 64;   // columns staged in LDS per step
 
-// Row tiles (16 rows) per wave: a workgroup covers 64 TL rows. Large n takes
-// four (the staged columns serve more rows); small n one, so that enough
+// Row tiles (16 rows) per wave: a workgroup covers 64 TL rows. From 2^17 rows
+// four (the staged columns serve more rows); below, one, so that enough
 // workgroups exist to fill the chip.
-inline int res_tiles(int64_t nr) { return nr >= (int64_t(1) << 20) ? 4 : (nr >= (1 << 17) ? 2 : 1); }
+inline int res_tiles(int64_t nr) { return nr >= (int64_t(1) << 17) ? 4 : 1; }
 
 typedef __attribute__((ext_vector_type(4))) double f64x4;
 
@@ -404,11 +404,10 @@ void launch_res_t(const Layout& L, const Params& P, const ResArgs& a, hipStream_
 
 template <int KERN, bool PRED>
 void launch_res_k(const Layout& L, const Params& P, const ResArgs& a, hipStream_t st) {
-  switch (res_tiles(a.nr)) {
-    case 4: launch_res_t<KERN, 4, PRED>(L, P, a, st); break;
-    case 2: launch_res_t<KERN, 2, PRED>(L, P, a, st); break;
-    default: launch_res_t<KERN, 1, PRED>(L, P, a, st); break;
-  }
+  if (res_tiles(a.nr) == 4)
+    launch_res_t<KERN, 4, PRED>(L, P, a, st);
+  else
+    launch_res_t<KERN, 1, PRED>(L, P, a, st);
 }
 
 template <bool PRED>

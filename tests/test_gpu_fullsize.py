@@ -114,3 +114,34 @@ def test_fullsize_updates_fp64_tiles_n2m():
 
 def test_fullsize_greedy_updates_split_tiles_n4m():
     _run(gen.c4(), ap.TILE_SPLIT)
+
+
+def test_fullsize_true_residual_sampled_rows():
+    """The FP64 true residual B - K^ W at n = 2M (l = 32, W ~ N(0, 1)) on 200
+    sampled rows and the ragged tail, against the oracle's rows. Both sides sum
+    2M FP64 terms per entry in different orders: the bound is 1e-12 of
+    sum_j |K^_ij| |W_jc| plus the FP32 storage of the result."""
+    w = gen.c3()
+    print(f"[fullsize-case] true residual n={w.n} l={w.l}", flush=True)
+    s, B, W, R = ap.from_workload(w, tile=ap.TILE_FP64)
+    rng = np.random.default_rng(8)
+    Wc = rng.standard_normal((w.n, w.l))
+    W.copy_(torch.from_numpy(Wc))
+    s.residual(B, W, R)
+    torch.cuda.synchronize()
+    Rg = R.cpu().numpy().astype(np.float64)
+    p = to_oracle(w)
+    rows = np.unique(np.concatenate([rng.choice(w.n, size=200, replace=False),
+                                     np.arange(w.n - 40, w.n)]))
+    ref = apo.residual_rows(p, Wc, rows)
+    # magnitude sum_j |K^_ij| |W_j| per row: the RBF row in numpy (bound only)
+    X64 = p.X
+    mag = np.empty((rows.size, w.l))
+    for r, i in enumerate(rows):
+        krow = p.outputscale * np.exp(-0.5 * (((X64 - X64[i]) / w.lengthscale) ** 2).sum(1))
+        krow[i] += p.noise
+        mag[r] = krow @ np.abs(Wc)
+    err = np.abs(Rg[rows] - ref)
+    bound = 1e-12 * mag + U32 * np.abs(ref) + 1e-300
+    print(f"[fullsize] true residual worst err/bound {np.max(err / bound):.3e}", flush=True)
+    assert np.all(err <= bound)
