@@ -1,6 +1,7 @@
-"""The FP64 tiles' table-driven exponential (Tang's method, in kmap64.h) on the
-host against long-double exp: compiled from the same header with hipcc and run
-on the CPU."""
+"""Device helpers compiled with hipcc for the host and run on the CPU: the FP64
+tiles' table-driven exponential (Tang's method, in kmap64.h) against
+long-double exp, and the random block rule (ap_internal.h) against the
+oracle's implementation."""
 from __future__ import annotations
 
 import os
