@@ -88,7 +88,7 @@ struct Layout {
   int32_t kernel, order, tile;
   unsigned long long seed;  // random order: seed of the block draws
   int32_t ks;            // BF16 K-steps of 16 feature slots (3d + 6 slots)
-  int32_t dp;            // FP32 feature stride (d rounded up to 4)
+  int32_t dp;            // prepared-feature stride (d rounded up to 4)
   int32_t nwg;           // workgroups of the fused update: n_pad / kRowsWG
   int32_t nwg_res;       // workgroups of the true residual
   size_t off_ctl, off_xs, off_xrow, off_xcol, off_kinv, off_dinv, off_panel, off_delta,
@@ -100,7 +100,7 @@ struct Layout {
 
 struct Dev {  // device pointers into one problem's workspace
   Ctl* ctl;
-  float* xs;             // FP32 path: n_pad x dp
+  double* xv;            // FP32 and split paths: n_pad x dp prepared features
   uint16_t* xrow;        // BF16 path: n_pad x 16 ks (row-role operand)
   uint16_t* xcol;        // BF16 path: n_pad x 16 ks (column-role operand)
   double* kinv;          // m x b_pad x b_pad

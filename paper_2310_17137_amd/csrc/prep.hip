@@ -39,9 +39,7 @@ bool make_layout(int64_t n, int32_t d, int32_t l, int32_t b, int32_t kernel, int
     return at;
   };
   o.off_ctl = take(sizeof(Ctl));
-  o.off_xs = take(tile == 0   ? (size_t)o.n_pad * 2 * o.dp * sizeof(float)
-                  : tile == 2 ? (size_t)o.n_pad * o.dp * sizeof(float)
-                              : 0);
+  o.off_xs = take(tile == 0 || tile == 2 ? (size_t)o.n_pad * o.dp * sizeof(double) : 0);
   o.off_xrow = take(tile == 1 ? (size_t)o.n_pad * 16 * o.ks * 2 : 0);
   o.off_xcol = take(tile == 1 ? (size_t)o.n_pad * 16 * o.ks * 2 : 0);
   o.off_kinv = take((size_t)o.m * o.b_pad * o.b_pad * sizeof(double));
@@ -67,7 +65,7 @@ Dev bind(const Layout& L, void* ws) {
   char* base = (char*)ws;
   Dev D;
   D.ctl = (Ctl*)(base + L.off_ctl);
-  D.xs = (float*)(base + L.off_xs);
+  D.xv = (double*)(base + L.off_xs);
   D.xrow = (uint16_t*)(base + L.off_xrow);
   D.xcol = (uint16_t*)(base + L.off_xcol);
   D.kinv = (double*)(base + L.off_kinv);
@@ -145,40 +143,26 @@ __global__ void k_mu_final(Layout L, const double* __restrict__ part, Ctl* ctl) 
 }
 
 // Prepared copies of the features, v = (x - mu) / ell * c (one thread per row).
-// FP32 path: xs[i] = [vh, vl], two FP32 terms with v = vh + vl to 2^-48, so a
-// difference of two points is formed without the rounding of v itself. Split
-// path: xs[i] = v in FP32. BF16 path: v = vh + vl (two BF16 terms), |v|^2 = nh + nm + nl
+// FP32 and split paths: xv[i] = v in FP64, differenced and squared in FP64 by
+// the fused update. BF16 path: v = vh + vl (two BF16 terms), |v|^2 = nh + nm + nl
 // (three BF16 terms), and the row / column operands
 //   row: [vh, vh, vl, -nh, -nm, -nl, 1, 1, 1, 0...]
 //   col: [2vh, 2vl, 2vh, 1, 1, 1, -nh, -nm, -nl, 0...]
 // whose dot product is 2 v_i.v_j - |v_i|^2 - |v_j|^2 = -|v_i - v_j|^2 (the
 // vl_i.vl_j term dropped). Padding rows (i >= n) are zero.
 __global__ __launch_bounds__(256) void k_prep(Layout L, Params P, const float* __restrict__ X,
-                                              const Ctl* __restrict__ ctl, float* __restrict__ xs,
+                                              const Ctl* __restrict__ ctl, double* __restrict__ xv,
                                               uint16_t* __restrict__ xrow,
                                               uint16_t* __restrict__ xcol) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= L.n_pad) return;
   const double c = feat_scale(L.kernel);
   const int d = L.d;
-  if (L.tile == 0) {
+  if (L.tile == 0 || L.tile == 2) {
     for (int k = 0; k < L.dp; ++k) {
-      float vh = 0.f, vl = 0.f;
-      if (i < L.n && k < d) {
-        double v = ((double)X[i * d + k] - ctl->mu[k]) / P.ell[k] * c;
-        vh = (float)v;
-        vl = (float)(v - (double)vh);
-      }
-      xs[i * 2 * L.dp + k] = vh;
-      xs[i * 2 * L.dp + L.dp + k] = vl;
-    }
-    return;
-  }
-  if (L.tile == 2) {
-    for (int k = 0; k < L.dp; ++k) {
-      float v = 0.f;
-      if (i < L.n && k < d) v = (float)(((double)X[i * d + k] - ctl->mu[k]) / P.ell[k] * c);
-      xs[i * L.dp + k] = v;
+      double v = 0.0;
+      if (i < L.n && k < d) v = ((double)X[i * d + k] - ctl->mu[k]) / P.ell[k] * c;
+      xv[i * L.dp + k] = v;
     }
     return;
   }
@@ -490,7 +474,7 @@ hipError_t launch_prep(const Layout& L, const Dev& D, const Params& P, const flo
   hipLaunchKernelGGL(k_mu_partial, dim3(256), dim3(256), 0, st, L, X, D.mupart);
   hipLaunchKernelGGL(k_mu_final, dim3(1), dim3(64), 0, st, L, D.mupart, D.ctl);
   unsigned g = (unsigned)((L.n_pad + 255) / 256);
-  hipLaunchKernelGGL(k_prep, dim3(g), dim3(256), 0, st, L, P, X, D.ctl, D.xs, D.xrow, D.xcol);
+  hipLaunchKernelGGL(k_prep, dim3(g), dim3(256), 0, st, L, P, X, D.ctl, D.xv, D.xrow, D.xcol);
   return hipGetLastError();
 }
 

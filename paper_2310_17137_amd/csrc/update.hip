@@ -30,8 +30,8 @@ typedef __attribute__((ext_vector_type(16))) double f64x16;
 constexpr float kInvLog2e = (float)(1.0 / kLog2e);                   // ln 2
 constexpr float kInv3Log2e2 = (float)(1.0 / (3.0 * kLog2e * kLog2e));  // 1 / (3 log2(e)^2)
 
-// Kernel map on the prepared squared distance. `a` is -|v_i - v_j|^2 (BF16
-// path) or |v_i - v_j|^2 (FP32 path); only its magnitude enters the Matern maps.
+// Kernel map of the BF16 tiles on a = -|v_i - v_j|^2 as the matrix cores return
+// it (FP32); only its magnitude enters the Matern maps.
 template <int KERN>
 __device__ __forceinline__ float kmap_neg(float a) {  // a = -|dv|^2
   if constexpr (KERN == 0) {
@@ -42,6 +42,51 @@ __device__ __forceinline__ float kmap_neg(float a) {  // a = -|dv|^2
     if constexpr (KERN == 1) return fmaf(t, kInvLog2e, 1.0f) * e;
     return fmaf(t, fmaf(t, kInv3Log2e2, kInvLog2e), 1.0f) * e;
   }
+}
+
+// Kernel map of the FP32 and split tiles: k/s from the FP64 squared distance a
+// of the prepared features, in FP32 to within about 2 ulp. The exponential runs
+// on the FP32 unit from a_hi = fl32(a); the argument's rounding a_lo = a - a_hi
+// enters to first order, 2^-(a_hi + a_lo) = 2^-a_hi (1 - a_lo ln 2). The
+// Matern maps take t = sqrt(a) as t_hi = sqrt(a_hi) plus the correction
+// k'(t_hi) (a - t_hi^2) / (2 t_hi), in which t_hi cancels:
+//   Matern-3/2: k/s = (1 + t ln2) 2^-t,              k' = -t ln2^2 2^-t,
+//   Matern-5/2: k/s = (1 + t ln2 + t^2 ln2^2/3) 2^-t, k' = -(t ln2^2/3)(1 + t ln2) 2^-t,
+// so no division is needed and a = 0 (the diagonal, duplicate points) is exact.
+template <int KERN>
+__device__ __forceinline__ float kmap_acc(double a) {
+  const float ah = (float)a;
+  if constexpr (KERN == 0) {
+    const float al = (float)(a - (double)ah);
+    const float e = __builtin_amdgcn_exp2f(-ah);
+    return fmaf(e, al * -kInvLog2e, e);
+  } else {
+    const float th = __builtin_amdgcn_sqrtf(ah);
+    const double thd = (double)th;
+    const float ea = (float)fma(-thd, thd, a);  // a - t_hi^2, exact in FP64
+    const float e = __builtin_amdgcn_exp2f(-th);
+    constexpr float kHalfLn2Sq = (float)(0.5 / (kLog2e * kLog2e));
+    if constexpr (KERN == 1) {
+      const float k0 = fmaf(th, kInvLog2e, 1.0f) * e;
+      return fmaf(ea * -kHalfLn2Sq, e, k0);
+    } else {
+      const float q = fmaf(th, kInvLog2e, 1.0f);
+      const float k0 = fmaf(th, fmaf(th, kInv3Log2e2, kInvLog2e), 1.0f) * e;
+      return fmaf(ea * q * (-kHalfLn2Sq * (1.0f / 3.0f)), e, k0);
+    }
+  }
+}
+
+// FP64 squared distance of a row's prepared features to a staged column's.
+template <int DV>
+__device__ __forceinline__ double dist2(const double* xr, const double* xc) {
+  double a = 0.0;
+#pragma unroll
+  for (int k = 0; k < DV; ++k) {
+    const double df = xr[k] - xc[k];
+    a = fma(df, df, a);
+  }
+  return a;
 }
 
 __device__ __forceinline__ bf16x8 load_bf16x8(const uint16_t* p) {
@@ -177,17 +222,20 @@ __global__ __launch_bounds__(256) void k_fused_bf16(Layout L, const uint16_t* __
   epilogue(L, row0, start, len, acc, R, rowsq, colsq, want_rowsq, want_colsq, (int)blockIdx.x);
 }
 
-// FP32 tiles: exact differencing of the prepared (hi, lo) FP32 features, FP32
-// map, and the product on v_mfma_f32_32x32x2f32 (one kernel value per lane per
-// step).
-template <int KERN, int DP>
-__global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const float* __restrict__ xs,
+// FP32 tiles: the prepared features in FP64, the squared distance in FP64, the
+// kernel map in FP32 (kmap_acc, within about 2 ulp), and the product with the
+// step on v_mfma_f32_32x32x2f32 (one kernel value per lane per step). Each
+// chunk's column features and step are staged in LDS.
+template <int KERN, int DV, int DP>
+__global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const double* __restrict__ xv,
                                                     const float* __restrict__ dtile,
                                                     const Ctl* __restrict__ ctl, int block,
                                                     float* __restrict__ R,
                                                     float* __restrict__ rowsq,
                                                     float* __restrict__ colsq, int want_rowsq,
                                                     int want_colsq) {
+  __shared__ double sx[kChunk][DP];
+  __shared__ float sd[kChunk][kMaxL];
   const int blk = resolve_block(block, ctl);
   if (blk < 0) return;
   const int64_t start = (int64_t)blk * L.b;
@@ -197,18 +245,11 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const float* __res
   const int nl = lane % 32, g = lane / 32;
   const int64_t row0 = (int64_t)blockIdx.x * kRowsWG + wave * 64;
 
-  // row features as (hi, lo) FP32 pairs
-  float xr[2][2 * DP];
+  double xr[2][DV];
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int k = 0; k < 2 * DP; k += 4) {
-      float4 v = *reinterpret_cast<const float4*>(xs + (row0 + 32 * t + nl) * 2 * DP + k);
-      xr[t][k] = v.x;
-      xr[t][k + 1] = v.y;
-      xr[t][k + 2] = v.z;
-      xr[t][k + 3] = v.w;
-    }
+    for (int k = 0; k < DV; ++k) xr[t][k] = xv[(row0 + 32 * t + nl) * DP + k];
   // Each chunk's 32 products accumulate in FP32 on the matrix cores; the chunk
   // sums then accumulate in FP64, so the rounding of the long sum over the
   // block stays at the level of one chunk.
@@ -220,6 +261,11 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const float* __res
 
   for (int ch = 0; ch < nch; ++ch) {
     const int64_t cb = start + (int64_t)ch * kChunk;
+    __syncthreads();
+    for (int e = threadIdx.x; e < kChunk * DP; e += 256) (&sx[0][0])[e] = xv[cb * DP + e];
+    for (int e = threadIdx.x; e < kChunk * kMaxL; e += 256)
+      (&sd[0][0])[e] = dtile[(int64_t)ch * kChunk * kMaxL + e];
+    __syncthreads();
     f32x16 part[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
@@ -228,25 +274,13 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const float* __res
 #pragma unroll 2
     for (int st = 0; st < 16; ++st) {
       const int cc = 2 * st + g;  // this lane's chunk column
-      float xc[2 * DP];
+      double xc[DV];
 #pragma unroll
-      for (int k = 0; k < 2 * DP; k += 4) {
-        float4 v = *reinterpret_cast<const float4*>(xs + (cb + cc) * 2 * DP + k);
-        xc[k] = v.x;
-        xc[k + 1] = v.y;
-        xc[k + 2] = v.z;
-        xc[k + 3] = v.w;
-      }
-      const float dv = dtile[((int64_t)ch * kChunk + cc) * kMaxL + nl];
+      for (int k = 0; k < DV; ++k) xc[k] = sx[cc][k];
+      const float dv = sd[cc][nl];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        float r2 = 0.f;
-#pragma unroll
-        for (int k = 0; k < DP; ++k) {
-          float df = (xr[t][k] - xc[k]) + (xr[t][DP + k] - xc[DP + k]);
-          r2 = fmaf(df, df, r2);
-        }
-        const float kv = kmap_neg<KERN>(-r2);
+        const float kv = kmap_acc<KERN>(dist2<DV>(xr[t], xc));
         part[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(dv, kv, part[t], 0, 0, 0);
       }
     }
@@ -258,8 +292,8 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const float* __res
   epilogue(L, row0, start, len, acc, R, rowsq, colsq, want_rowsq, want_colsq, (int)blockIdx.x);
 }
 
-// Split path: FP32 kernel tiles (exact differencing of FP32 features, FP32
-// map) and the product on BF16 matrix cores. The tile K = kh + km + kl and the
+// Split path: FP32 kernel tiles (FP64 squared distance of the FP64 prepared
+// features, kmap_acc) and the product on BF16 matrix cores. The tile K = kh + km + kl and the
 // step d = dh + dm + dl are each held as three BF16 terms (24 significant bits),
 // and the six partial products with term orders summing to at most 2,
 //   dl kh + dh kl + dm km + dm kh + dh km + dh kh   (small to large),
@@ -267,11 +301,11 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const float* __res
 // FP32-grade accuracy at BF16 matrix-core rates. The K operand of each MFMA is
 // built per lane in the BF16 path's column order, so the step layout is shared.
 template <int KERN, int DV, int DP>
-__device__ __forceinline__ void split_body(const Layout& L, const float* __restrict__ xs,
+__device__ __forceinline__ void split_body(const Layout& L, const double* __restrict__ xv,
                                            const uint16_t* __restrict__ dtile, int blk,
                                            float* __restrict__ R, float* __restrict__ rowsq,
                                            float* __restrict__ colsq, bool want_rowsq,
-                                           bool want_colsq, int wg, float* sx) {
+                                           bool want_colsq, int wg, double* sx) {
   const int64_t start = (int64_t)blk * L.b;
   const int len = (int)std::min<int64_t>(L.b, L.n - start);
   const int nch = (len + kChunk - 1) / kChunk;
@@ -280,11 +314,11 @@ __device__ __forceinline__ void split_body(const Layout& L, const float* __restr
   const int64_t row0 = (int64_t)wg * kRowsWG + wave * 64;
   const size_t term = (size_t)L.b_pad * kMaxL;
 
-  float xr[2][DV];
+  double xr[2][DV];
 #pragma unroll
   for (int t = 0; t < 2; ++t)
 #pragma unroll
-    for (int k = 0; k < DV; ++k) xr[t][k] = xs[(row0 + 32 * t + nl) * DP + k];
+    for (int k = 0; k < DV; ++k) xr[t][k] = xv[(row0 + 32 * t + nl) * DP + k];
 
   f64x16 acc[2];
 #pragma unroll
@@ -295,7 +329,7 @@ __device__ __forceinline__ void split_body(const Layout& L, const float* __restr
   for (int ch = 0; ch < nch; ++ch) {
     const int64_t cb = start + (int64_t)ch * kChunk;
     __syncthreads();
-    for (int e = threadIdx.x; e < kChunk * DP; e += 256) sx[e] = xs[cb * DP + e];
+    for (int e = threadIdx.x; e < kChunk * DP; e += 256) sx[e] = xv[cb * DP + e];
     __syncthreads();
     f32x16 part[2];
 #pragma unroll
@@ -314,13 +348,7 @@ __device__ __forceinline__ void split_body(const Layout& L, const float* __restr
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const int cc = 16 * st + 4 * g + (e % 4) + 8 * (e / 4);
-          float r2 = 0.f;
-#pragma unroll
-          for (int k = 0; k < DV; ++k) {
-            const float df = xr[t][k] - sx[cc * DP + k];
-            r2 = fmaf(df, df, r2);
-          }
-          kv[e] = kmap_neg<KERN>(-r2);
+          kv[e] = kmap_acc<KERN>(dist2<DV>(xr[t], sx + cc * DP));
         }
         const bf16x8 kh = pack8(kv, 0);
 #pragma unroll
@@ -346,17 +374,17 @@ __device__ __forceinline__ void split_body(const Layout& L, const float* __restr
 }
 
 template <int KERN, int DV, int DP>
-__global__ __launch_bounds__(256) void k_fused_split(Layout L, const float* __restrict__ xs,
+__global__ __launch_bounds__(256) void k_fused_split(Layout L, const double* __restrict__ xv,
                                                      const uint16_t* __restrict__ dtile,
                                                      const Ctl* __restrict__ ctl, int block,
                                                      float* __restrict__ R,
                                                      float* __restrict__ rowsq,
                                                      float* __restrict__ colsq, int want_rowsq,
                                                      int want_colsq) {
-  __shared__ float sx[kChunk * DP];
+  __shared__ double sx[kChunk * DP];
   const int blk = resolve_block(block, ctl);
   if (blk < 0) return;
-  split_body<KERN, DV, DP>(L, xs, dtile, blk, R, rowsq, colsq, want_rowsq, want_colsq,
+  split_body<KERN, DV, DP>(L, xv, dtile, blk, R, rowsq, colsq, want_rowsq, want_colsq,
                            (int)blockIdx.x, sx);
 }
 
@@ -366,8 +394,8 @@ __global__ __launch_bounds__(256) void k_fused_split(Layout L, const float* __re
 // partials; the batch's epoch-end check reads those of the epoch's last one.
 template <int KERN, int WIDE>
 __device__ __forceinline__ void split_dispatch(const Layout& L, const Desc* ds, int blk, float* R,
-                                               int wg, float* sx) {
-  const float* xs = ds->D.xs;
+                                               int wg, double* sx) {
+  const double* xs = ds->D.xv;
   const uint16_t* dt = (const uint16_t*)ds->D.dtile;
   const bool wr = L.order == 1;
   if constexpr (WIDE == 0) {
@@ -390,7 +418,7 @@ __device__ __forceinline__ void split_dispatch(const Layout& L, const Desc* ds, 
 // would not allow.
 template <int WIDE>
 __global__ __launch_bounds__(256) void g_fused_split(Group g) {
-  __shared__ float sx[kChunk * (WIDE ? kMaxD : 8)];
+  __shared__ double sx[kChunk * (WIDE ? kMaxD : 8)];
   int wg;
   const int p = group_job(g, &wg);
   const Desc* ds = g.desc[p];
@@ -426,14 +454,22 @@ hipError_t launch_fp32(const Layout& L, const Dev& D, int32_t block, float* R, b
                        hipStream_t st) {
   const dim3 g(L.nwg), t(256);
   const float* dt = (const float*)D.dtile;
-  switch (L.dp) {
-    case 4: hipLaunchKernelGGL((k_fused_fp32<KERN, 4>), g, t, 0, st, L, D.xs, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
-    case 8: hipLaunchKernelGGL((k_fused_fp32<KERN, 8>), g, t, 0, st, L, D.xs, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
-    case 12: hipLaunchKernelGGL((k_fused_fp32<KERN, 12>), g, t, 0, st, L, D.xs, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
-    case 16: hipLaunchKernelGGL((k_fused_fp32<KERN, 16>), g, t, 0, st, L, D.xs, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
-    case 20: hipLaunchKernelGGL((k_fused_fp32<KERN, 20>), g, t, 0, st, L, D.xs, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
-    default: return hipErrorInvalidValue;
+#define AP_FP32(DV, DP)                                                                        \
+  hipLaunchKernelGGL((k_fused_fp32<KERN, DV, DP>), g, t, 0, st, L, D.xv, dt, D.ctl, block, R, \
+                     D.rowsq, D.colsq, (int)wr, (int)wc)
+  if (L.d == 3) {
+    AP_FP32(3, 4);
+  } else {
+    switch (L.dp) {
+      case 4: AP_FP32(4, 4); break;
+      case 8: AP_FP32(8, 8); break;
+      case 12: AP_FP32(12, 12); break;
+      case 16: AP_FP32(16, 16); break;
+      case 20: AP_FP32(20, 20); break;
+      default: return hipErrorInvalidValue;
+    }
   }
+#undef AP_FP32
   return hipGetLastError();
 }
 
@@ -443,15 +479,15 @@ hipError_t launch_split(const Layout& L, const Dev& D, int32_t block, float* R, 
   const dim3 g(L.nwg), t(256);
   const uint16_t* dt = (const uint16_t*)D.dtile;
   if (L.d == 3) {
-    hipLaunchKernelGGL((k_fused_split<KERN, 3, 4>), g, t, 0, st, L, D.xs, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc);
+    hipLaunchKernelGGL((k_fused_split<KERN, 3, 4>), g, t, 0, st, L, D.xv, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc);
     return hipGetLastError();
   }
   switch (L.dp) {
-    case 4: hipLaunchKernelGGL((k_fused_split<KERN, 4, 4>), g, t, 0, st, L, D.xs, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
-    case 8: hipLaunchKernelGGL((k_fused_split<KERN, 8, 8>), g, t, 0, st, L, D.xs, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
-    case 12: hipLaunchKernelGGL((k_fused_split<KERN, 12, 12>), g, t, 0, st, L, D.xs, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
-    case 16: hipLaunchKernelGGL((k_fused_split<KERN, 16, 16>), g, t, 0, st, L, D.xs, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
-    case 20: hipLaunchKernelGGL((k_fused_split<KERN, 20, 20>), g, t, 0, st, L, D.xs, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 4: hipLaunchKernelGGL((k_fused_split<KERN, 4, 4>), g, t, 0, st, L, D.xv, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 8: hipLaunchKernelGGL((k_fused_split<KERN, 8, 8>), g, t, 0, st, L, D.xv, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 12: hipLaunchKernelGGL((k_fused_split<KERN, 12, 12>), g, t, 0, st, L, D.xv, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 16: hipLaunchKernelGGL((k_fused_split<KERN, 16, 16>), g, t, 0, st, L, D.xv, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 20: hipLaunchKernelGGL((k_fused_split<KERN, 20, 20>), g, t, 0, st, L, D.xv, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -9,11 +9,15 @@ see the same FP32 values (the oracle widened to FP64). Tolerances:
     rounding of K^_{:,I} delta: ||dR|| <= 1e-5 ||R|| + 2 u32 || |K^_{:,I}| |delta| ||
     (u32 = 2^-24). Where that amplification factor || |K||delta| || / ||R|| is
     large (ill-conditioned cases) the iterates inherit it, and the bar becomes
-    4 u32 times the factor. Over several epochs the bar is also at least 8
-    times the rounding floor: the distance from the oracle of the same
-    trajectory with every kernel value rounded once to FP32 (an emulation on
-    the CPU); the GPU's kernel values are within 8 ulps (the unit-block column
-    test below checks that) where correct rounding is within half an ulp;
+    4 u32 times the factor. Over several epochs the bar is at most twice the
+    FP32-tile floor (tests.helpers.fp32_tile_floor): the distance from the
+    oracle of a perfect FP32-tile run of the same updates (kernel values and
+    step correctly rounded to FP32, 32-column chunks summed in FP32, emulated
+    on the CPU), printed with the GPU's error for every epoch. The FP32 sums
+    inside each chunk, not the kernel values, set that floor: on the 4096-point
+    recipe it is 3.4e-5 after 30 epochs, against 7e-6 with the kernel values
+    rounded and FP64 sums. The GPU's kernel values are within about 2 ulp (the
+    unit-block column test checks that);
   - BF16 tiles: one update within 2e-2 relative; solves reach a true FP64
     relative residual below the tolerance;
   - FP64 true residual: 1e-9 relative to ||B||.
@@ -25,7 +29,7 @@ import pytest
 
 from oracle import apo
 from paper_2310_17137_amd import gen
-from tests.helpers import dense_khat, fp32_rounding_floor, to_oracle
+from tests.helpers import dense_khat, fp32_tile_floor, to_oracle
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -124,14 +128,17 @@ def test_epochs_fp32_match_oracle(case):
     L = apo.factor(p)
     K = dense_khat(p)
     tol = _epoch_tol(p, L, K) if p.m > 1 else 1e-5
-    tol = max(tol, 8 * fp32_rounding_floor(p, 3))
+    floor = fp32_tile_floor(p, 3)
+    tol = max(tol, 2 * max(floor))
     print(f"[tol] W iterates within {tol:.2e}", flush=True)
     Wo, Ro = np.zeros_like(p.B), p.B.copy()
     for ep in range(3):
         s.epoch(B, W, R, 1)
         apo.epoch(p, L, Wo, Ro)
         rho, cols = s.rel_residual()
-        assert _rel(W.cpu().numpy(), Wo) < tol, ep
+        e = _rel(W.cpu().numpy(), Wo)
+        print(f"[fp32] epoch {ep + 1} W err {e:.3e} floor {floor[ep]:.3e}", flush=True)
+        assert e < tol, ep
         rho_o = apo.rel_residual(p, Ro)
         assert abs(rho - rho_o) <= max(tol * rho_o, 1e-7)
 
@@ -356,13 +363,16 @@ def test_true_residual_fp64(case):
 
 def test_c1_trajectory_fp32():
     """C1 (n = 4096, RBF, b = 512, one RHS): 30 epochs against the oracle. The
-    target is 1e-5; FP32 rounding of the kernel values alone puts the iterates
-    7e-6 (3 epochs) from the oracle's, so the bar is max(1e-5, 8 x floor)."""
+    target is 1e-5. A perfect FP32-tile run is already 3.4e-5 from the oracle
+    (the FP32 sums inside each 32-column chunk; kernel values rounded to FP32
+    with FP64 sums give 7e-6), so the bar is max(1e-5, 2 x that floor); the
+    floor and the GPU's error are printed for every epoch."""
     w = gen.c1()
     s, B, W, R = _gpu(w)
     s.reset(B, W, R)
     p = to_oracle(w)
-    tol = max(1e-5, 8 * fp32_rounding_floor(p, 30))
+    floor = fp32_tile_floor(p, 30)
+    tol = max(1e-5, 2 * max(floor))
     print(f"[c1] tolerance {tol:.3e}", flush=True)
     L = apo.factor(p)
     Wo, Ro = np.zeros_like(p.B), p.B.copy()
@@ -373,7 +383,8 @@ def test_c1_trajectory_fp32():
         rho, _ = s.rel_residual()
         e = _rel(W.cpu().numpy(), Wo)
         rho_o = apo.rel_residual(p, Ro)
-        print(f"[c1] epoch {ep + 1} rho {rho:.8f} oracle {rho_o:.8f} W err {e:.3e}", flush=True)
+        print(f"[c1] epoch {ep + 1} rho {rho:.8f} oracle {rho_o:.8f} W err {e:.3e} "
+              f"floor {floor[ep]:.3e}", flush=True)
         worst = max(worst, e)
         assert rho == pytest.approx(rho_o, rel=1e-4)  # a norm of the FP32 residual
     assert worst < tol
@@ -403,8 +414,10 @@ def test_solve_fp32_matches_oracle_solve():
     res = apo.solve(p)
     assert st.converged == res.converged
     assert st.epochs == res.epochs
-    tol = max(1e-5, 8 * fp32_rounding_floor(p, st.epochs))
-    assert _rel(W.cpu().numpy(), res.W) < tol
+    tol = max(1e-5, 2 * max(fp32_tile_floor(p, st.epochs)))
+    e = _rel(W.cpu().numpy(), res.W)
+    print(f"[solve-fp32] {st.epochs} epochs, W err {e:.3e}, bar {tol:.3e}", flush=True)
+    assert e < tol
 
 
 def test_not_positive_definite_reports_block():
@@ -456,10 +469,11 @@ def test_kernel_column_through_unit_blocks(kern, tile):
     """With b = 1 every block is one point j, the step is R_j / (s + sigma^2)
     and one update subtracts that step times the kernel column k(x_:, x_j): the
     change of R reads out the GPU's kernel values one column at a time.
-    FP32-grade tiles: a kernel value computed from an FP32 exponent argument
-    carries that argument's relative error times |ln(k/s)| (the condition
-    number of exp), so the bound is u32 (4 |R| + (4 + 4 |ln(k/s)|) |k delta|);
-    FP64 tiles meet the same bound with room; BF16 tiles: 2^-7 |R| + |k delta|."""
+    FP32-grade tiles: kernel values within about 2 ulp at every magnitude (the
+    exponent's argument is carried to FP64 accuracy), the step and the product
+    rounded once each, R stored in FP32: the bound is u32 (4 |R| + 6 |k delta|);
+    FP64 tiles meet the same bound with room. BF16 tiles (8-bit products, the
+    exponent's argument from BF16 products): 2^-7 |R| + |k delta|."""
     rng = np.random.default_rng(11)
     w = gen.small(12, 1500, 5, 3, 1, kernel=kern, noise=0.05,
                   ell=rng.uniform(0.15, 0.6, size=5), outputscale=1.7)
@@ -476,13 +490,10 @@ def test_kernel_column_through_unit_blocks(kern, tile):
         torch.cuda.synchronize()
         Rg = R.cpu().numpy().astype(np.float64)
         kcol = np.abs(K[:, j:j + 1])
-        kcol_noiseless = kcol.copy()
-        kcol_noiseless[j] -= p.noise
-        cond = np.abs(np.log(np.maximum(kcol_noiseless / p.outputscale, 1e-300)))
         if tile == ap.TILE_BF16:
             rel, mag = 2.0 ** -7, np.abs(R0) + kcol * np.abs(delta)
         else:
-            rel, mag = U32, 4 * np.abs(R0) + (4 + 4 * cond) * kcol * np.abs(delta)
+            rel, mag = U32, 4 * np.abs(R0) + 6 * kcol * np.abs(delta)
         err = np.abs(Rg - Ro)
         err[j] = 0.0  # the selected row is zeroed by both
         print(f"[column] kern {kern} tile {tile} j {j}: worst err/bound "
@@ -529,3 +540,4 @@ def test_solve_escalates_to_fp64_tiles():
     drift = float((R - Rt).norm() / Rt.norm())
     print(f"[escalate] maintained vs true after the solve {drift:.3e}", flush=True)
     assert drift < 1e-4
+
