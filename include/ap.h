@@ -131,6 +131,9 @@ typedef struct {
   double t_refine;            /* seconds in true-residual passes */
   int32_t tile;               /* ap_tile in use when the solve ended */
   int32_t escalated_at;       /* epoch after which FP64 tiles took over, -1 if never */
+  int32_t restarted_at;       /* epoch after which the solve restarted from W = 0 on
+                                 FP64 tiles (non-finite norms, or a drifted W whose
+                                 true ratio was >= 1), -1 if never */
 } ap_stats;
 
 typedef struct ap_problem* ap_handle;
@@ -185,11 +188,13 @@ ap_status ap_rel_residual(ap_handle h, hipStream_t stream, double* rho, double* 
  * replaced by the FP64 true residual (exact by Lemma residual_equality) and the
  * test is repeated on it; the interval between these scheduled true residuals
  * doubles, up to 16 refine_every, while the true and maintained ratios agree to
- * 1e-5, and returns to refine_every when they do not. If that true residual's ratio and the maintained one
- * differ by more than 5%, the rest of the solve runs on FP64 tiles from the
- * current W; if an epoch's norms are not finite, the solve restarts from W = 0
- * on FP64 tiles (stats.tile, stats.escalated_at). The handle's own mode is
- * unchanged afterwards. Synchronizes once per epoch. Returns AP_OK,
+ * 1e-5, and returns to refine_every when they do not. If that true residual's
+ * ratio and the maintained one differ by more than 5%, the rest of the solve
+ * runs on FP64 tiles: from the current W when its true ratio is below 1 (the
+ * ratio of W = 0), else from W = 0; if an epoch's norms are not finite, the
+ * solve restarts from W = 0 on FP64 tiles (stats.tile, stats.escalated_at,
+ * stats.restarted_at). The handle's tile mode on return, errors included, is
+ * the one it had on entry. Synchronizes once per epoch. Returns AP_OK,
  * AP_NOT_CONVERGED or an error; out [host, may be NULL] gets the statistics. */
 ap_status ap_solve(ap_handle h, const ap_state* st, hipStream_t stream, ap_stats* out);
 

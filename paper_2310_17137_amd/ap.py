@@ -52,7 +52,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("epochs", ctypes.c_int32), ("refines", ctypes.c_int32),
                 ("rho_maintained", ctypes.c_double), ("rho_true", ctypes.c_double),
                 ("t_epochs", ctypes.c_double), ("t_refine", ctypes.c_double),
-                ("tile", ctypes.c_int32), ("escalated_at", ctypes.c_int32)]
+                ("tile", ctypes.c_int32), ("escalated_at", ctypes.c_int32),
+                ("restarted_at", ctypes.c_int32)]
 
 
 # ap_batch_state: why a problem of a batch is held
@@ -194,6 +195,7 @@ class SolveStats:
     t_refine: float
     tile: int = 0
     escalated_at: int = -1
+    restarted_at: int = -1
 
     @property
     def converged(self) -> bool:
@@ -293,7 +295,7 @@ class Solver:
         code = fn(self.handle, ctypes.byref(st), _stream(stream), ctypes.byref(s))
         _check(code, "ap_solve_from" if warm else "ap_solve", ok=(OK, NOT_CONVERGED))
         return SolveStats(code, s.epochs, s.refines, s.rho_maintained, s.rho_true, s.t_epochs,
-                          s.t_refine, s.tile, s.escalated_at)
+                          s.t_refine, s.tile, s.escalated_at, s.restarted_at)
 
     def residual(self, B, W, R, R_out=None, want_col_rel: bool = True, stream=None):
         """FP64 true residual into R_out (None: refine R in place)."""

@@ -375,9 +375,17 @@ static ap_status solve_impl(ap_handle h, const ap_state* st, hipStream_t stream,
                             bool warm) {
   if (!valid_handle(h) || !valid_state(st)) return AP_ERR_INVALID_ARG;
   const ap_config& c = h->cfg;
+  // The solve may move to FP64 tiles; the mode the handle held on entry (its
+  // configured one, or FP64 after ap_set_tile) is put back on every return.
+  struct TileGuard {
+    ap_problem* h;
+    int32_t tile;
+    ~TileGuard() { h->L.tile = tile; }
+  } guard{h, h->L.tile};
   ap_stats s{};
   s.rho_true = NAN;
   s.escalated_at = -1;
+  s.restarted_at = -1;
   ap_status r = warm ? ap_warm_start(h, st, stream) : ap_reset(h, st, stream);
   if (r != AP_OK) return r;
   ap_status result = AP_NOT_CONVERGED;
@@ -400,6 +408,7 @@ static ap_status solve_impl(ap_handle h, const ap_state* st, hipStream_t stream,
       if (h->L.tile == AP_TILE_FP64) return AP_ERR_NONFINITE;
       h->L.tile = AP_TILE_FP64;
       s.escalated_at = t;
+      s.restarted_at = t;
       r = ap_reset(h, st, stream);
       if (r != AP_OK) return r;
       s.epochs = t;
@@ -436,6 +445,15 @@ static ap_status solve_impl(ap_handle h, const ap_state* st, hipStream_t stream,
       if (h->L.tile != AP_TILE_FP64 && drift > 0.05) {
         h->L.tile = AP_TILE_FP64;
         s.escalated_at = t;
+        if (ctl.rho_true >= 1.0) {
+          // the drifted W is no better than W = 0 (ratio 1): restart
+          // Algorithm 1 from W = 0 on FP64 tiles instead of continuing from it
+          s.restarted_at = t;
+          r = ap_reset(h, st, stream);
+          if (r != AP_OK) return r;
+          if (scheduled) next_ref = t + c.refine_every;
+          continue;
+        }
       }
       if (scheduled) {
         interval = drift < 1e-5 ? std::min(2 * interval, 16 * c.refine_every) : c.refine_every;
@@ -450,7 +468,6 @@ static ap_status solve_impl(ap_handle h, const ap_state* st, hipStream_t stream,
   s.t_epochs = t_ep;
   s.t_refine = t_ref;
   s.tile = h->L.tile;
-  h->L.tile = h->cfg.tile;  // the handle keeps its configured mode
   if (out) *out = s;
   return result;
 }

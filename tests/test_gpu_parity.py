@@ -534,6 +534,8 @@ def test_solve_escalates_to_fp64_tiles():
     st = s.solve(B, W, R)
     print(f"[escalate] {st}", flush=True)
     assert st.tile == ap.TILE_FP64 and 1 <= st.escalated_at <= 2
+    # a restart from W = 0 happens at the escalation or not at all
+    assert st.restarted_at in (-1, st.escalated_at)
     assert np.isfinite(st.rho_true) and np.isfinite(st.rho_maintained)
     Rt = torch.empty_like(R)
     s.residual(B, W, R, R_out=Rt)
@@ -541,3 +543,48 @@ def test_solve_escalates_to_fp64_tiles():
     print(f"[escalate] maintained vs true after the solve {drift:.3e}", flush=True)
     assert drift < 1e-4
 
+
+def _same_update(sa, sb, w, B, W, R, blk):
+    """One update on block blk by two handles from the same (W, R): bitwise
+    equal results mean the same tile arithmetic."""
+    Wa, Ra, Wb, Rb = W.clone(), R.clone(), W.clone(), R.clone()
+    sa.update(B, Wa, Ra, blk)
+    sb.update(B, Wb, Rb, blk)
+    torch.cuda.synchronize()
+    return torch.equal(Ra, Rb) and torch.equal(Wa, Wb)
+
+
+def test_solve_keeps_a_tile_set_by_the_caller():
+    """ap_set_tile(FP64) on a split-tile handle, then ap_solve: the handle is
+    still on FP64 tiles afterwards (its next update is bitwise an FP64-tile
+    handle's, not a split-tile handle's)."""
+    w = _small(CASES[1])
+    w.max_epochs = 3
+    s, B, W, R = _gpu(w, tile=ap.TILE_SPLIT)
+    s.set_tile(ap.TILE_FP64)
+    st = s.solve(B, W, R)
+    assert st.tile == ap.TILE_FP64 and st.escalated_at == -1
+    ref64, _, _, _ = _gpu(w, tile=ap.TILE_FP64)
+    ref_split, _, _, _ = _gpu(w, tile=ap.TILE_SPLIT)
+    assert _same_update(s, ref64, w, B, W, R, 1)
+    assert not _same_update(s, ref_split, w, B, W, R, 1)
+
+
+def test_solve_error_after_escalation_restores_the_tile():
+    """A NaN in B: the first epoch's norms are not finite, the solve restarts
+    on FP64 tiles, fails there too and returns AP_ERR_NONFINITE. The handle
+    is back on its BF16 tiles afterwards (bitwise a fresh BF16 handle's next
+    update on finite data)."""
+    w = _small(CASES[0])
+    s, B, W, R = _gpu(w, tile=ap.TILE_BF16)
+    Bbad = B.clone()
+    Bbad[5, 0] = float("nan")
+    with pytest.raises(ap.ApError) as e:
+        s.solve(Bbad, W, R)
+    assert e.value.code == ap.ERR_NONFINITE
+    ref16, _, _, _ = _gpu(w, tile=ap.TILE_BF16)
+    ref64, _, _, _ = _gpu(w, tile=ap.TILE_FP64)
+    s.reset(B, W, R)
+    s.epoch(B, W, R, 1)
+    assert _same_update(s, ref16, w, B, W, R, 2)
+    assert not _same_update(s, ref64, w, B, W, R, 2)
