@@ -216,6 +216,30 @@ ap_status ap_solve_from(ap_handle h, const ap_state* st, hipStream_t stream, ap_
 ap_status ap_residual(ap_handle h, const ap_state* st, float* R_out, double* col_rel,
                       hipStream_t stream);
 
+/* For callers that cannot allocate device memory and keep no solver workspace
+ * (code under HIP graph capture, serving loops and harnesses that forbid
+ * hipMalloc): ap_residual's FP64 true residual R_out = B - K^ W (Lemma
+ * residual_equality) without a handle, for the kernel and hyperparameters in
+ * cfg (n, d, l, kernel, lengthscale, outputscale, noise; the block size,
+ * order, tile and stopping fields are not used). Same kernels as ap_residual:
+ * R_out and col_rel are bitwise what ap_residual gives after ap_reset of the
+ * same B.
+ *  X     [dev] n x d FP32;  B [dev] n x l FP32;  W [dev] n x l FP64;
+ *  R_out [dev] n x l FP32, written;
+ *  col_rel [host, may be NULL] the l ratios ||r_c|| / ||b_c|| of the FP64
+ *          values (passing it synchronizes the stream; pass NULL under capture).
+ * Its scratch (column norms, ratios and per-workgroup column partials) is a
+ * device array of AP_NOALLOC_SCRATCH_BYTES that the library holds on every GPU
+ * it runs on until the process ends; the call allocates nothing. n above
+ * AP_NOALLOC_MAX_N returns AP_ERR_UNSUPPORTED. All calls on one GPU share that
+ * GPU's scratch, which keeps the last call's contents: calls that overlap on
+ * one device (other streams, other threads) race, so the caller orders them. */
+#define AP_NOALLOC_MAX_N 4194304
+#define AP_NOALLOC_SCRATCH_BYTES 4198400
+ap_status ap_residual_noalloc(const ap_config* cfg, const float* X, const float* B,
+                              const double* W, float* R_out, double* col_rel,
+                              hipStream_t stream);
+
 /* Stochastic gradient of the negative log marginal likelihood
  * (y^T K^^{-1} y + log det K^) / 2 (Section 2, eq. loss_grad_unbiased) from a
  * solve's W = K^^{-1} B, where B = [y, z_1, .., z_P] holds the targets and

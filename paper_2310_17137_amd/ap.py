@@ -29,7 +29,8 @@ SYMBOLS = ("ap_workspace_bytes", "ap_factor_blocks", "ap_reset", "ap_epoch", "ap
            "ap_rel_residual", "ap_solve", "ap_solve_from", "ap_warm_start", "ap_residual", "ap_block_inverse", "ap_set_tile",
            "ap_profile",
            "ap_profile_read", "ap_predict", "ap_mll_grad", "ap_batch_step", "ap_batch_peek", "ap_batch_release",
-           "ap_destroy", "ap_status_str", "ap_last_error")
+           "ap_destroy", "ap_status_str", "ap_last_error", "ap_residual_noalloc")
+NOALLOC_MAX_N = 4194304
 PHASES = ("block_solve", "fused_update", "select", "epoch_check", "true_residual")
 
 
@@ -126,6 +127,7 @@ def load():
             "ap_solve_from": (I32, [P, S, P, St]),
             "ap_warm_start": (I32, [P, S, P]),
             "ap_residual": (I32, [P, S, P, D, P]),
+            "ap_residual_noalloc": (I32, [C, P, P, P, P, D, P]),
             "ap_block_inverse": (I32, [P, I32, P, P]),
             "ap_predict": (I32, [P, P, P, I64, P, P]),
             "ap_mll_grad": (I32, [P, S, D, P, P]),
@@ -371,6 +373,30 @@ class Solver:
         _check(load().ap_block_inverse(self.handle, int(j), ctypes.c_void_p(out.data_ptr()),
                                        _stream(stream)), "ap_block_inverse")
         return out
+
+
+def residual_noalloc(X, B, W, R_out, *, kernel: int, lengthscale, outputscale=1.0, noise=0.1,
+                     want_col_rel: bool = True, stream=None):
+    """ap_residual_noalloc: R_out = B - K^ W in FP64 (written as FP32) with no
+    handle and no workspace; returns the per-column ratios (synchronizes) or
+    None."""
+    import torch
+    for t, dt in ((X, torch.float32), (B, torch.float32), (W, torch.float64),
+                  (R_out, torch.float32)):
+        if not (t.is_cuda and t.dtype == dt and t.dim() == 2 and t.is_contiguous()):
+            raise ValueError("X, B, R_out: contiguous float32 CUDA tensors; W: float64")
+    n, d = X.shape
+    l = B.shape[1]
+    if B.shape != (n, l) or W.shape != (n, l) or R_out.shape != (n, l):
+        raise ValueError("B, W and R_out must be n x l")
+    cfg, _ls = make_config(n, d, l, min(n, 4096), kernel, lengthscale, outputscale, noise)
+    cols = (ctypes.c_double * l)() if want_col_rel else None
+    _check(load().ap_residual_noalloc(ctypes.byref(cfg), ctypes.c_void_p(X.data_ptr()),
+                                      ctypes.c_void_p(B.data_ptr()),
+                                      ctypes.c_void_p(W.data_ptr()),
+                                      ctypes.c_void_p(R_out.data_ptr()), cols, _stream(stream)),
+           "ap_residual_noalloc")
+    return None if cols is None else np.array(cols[:], dtype=np.float64)
 
 
 def epoch_many(solvers, states, epochs: int = 1, stream=None):

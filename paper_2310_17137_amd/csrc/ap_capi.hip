@@ -217,6 +217,12 @@ ap_status run_epoch(ap_problem* h, const ap_state* st, hipStream_t s) {
 
 }  // namespace
 
+namespace ap {
+int note_error(const char* where, hipError_t e) { return (int)note_hip(e, where); }
+void note_text(const char* msg) { std::snprintf(g_last_error, sizeof(g_last_error), "%s", msg); }
+void take_foreign_error() { clear_foreign_error(); }
+}  // namespace ap
+
 extern "C" {
 
 size_t ap_workspace_bytes(const ap_config* cfg) {

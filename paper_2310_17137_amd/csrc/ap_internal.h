@@ -152,6 +152,14 @@ __device__ __forceinline__ int group_job(const Group& g, int* local) {
   return p;
 }
 
+// Record a failure for ap_last_error (this thread): a HIP call and its error,
+// or a plain message. note_error returns AP_ERR_HIP (-5).
+int note_error(const char* where, hipError_t e);
+void note_text(const char* msg);
+// Take off (and keep for ap_last_error) an error an earlier HIP call outside
+// the library left unread, before launching.
+void take_foreign_error();
+
 bool make_layout(int64_t n, int32_t d, int32_t l, int32_t b, int32_t kernel, int32_t order,
                  int32_t tile, Layout* L);
 Dev bind(const Layout& L, void* ws);
@@ -161,9 +169,15 @@ hipError_t launch_prep(const Layout& L, const Dev& D, const Params& P, const flo
                        hipStream_t st);
 hipError_t launch_factor(const Layout& L, const Dev& D, const Params& P, const float* X,
                          hipStream_t st);
+// Workgroups of the reset's column-norm partials (D.respart holds as many rows).
+constexpr int kResetGroups = 1024;
 // R = B, the column norms of B, a fresh control block; W = 0 unless keep_w
 hipError_t launch_reset(const Layout& L, const Dev& D, const float* B, double* W, float* R,
                         bool keep_w, hipStream_t st);
+// only the column norms of B and a fresh control block (D.ctl, D.respart)
+hipError_t launch_bnorm(const Layout& L, const Dev& D, const float* B, hipStream_t st);
+// workgroups of the true residual over n rows (its column partials in D.respart)
+int residual_groups(int64_t n);
 // block: >= 0, kBlockSel or a batch code (see resolve_block)
 hipError_t launch_block_solve(const Layout& L, const Dev& D, const Params& P, int32_t block,
                               const float* R, double* W, hipStream_t st);

@@ -215,13 +215,15 @@ __global__ __launch_bounds__(256) void k_prep(Layout L, Params P, const float* _
 }
 
 // W = 0, R = B (Algorithm 1 initialization), per-row sums of squares of B, and
-// per-workgroup FP64 column partials of ||B_c||^2.
+// per-workgroup FP64 column partials of ||B_c||^2. With R == nullptr only the
+// column partials are formed (W, R and rowsq untouched).
 __global__ __launch_bounds__(256) void k_reset(Layout L, const float* __restrict__ B,
                                                double* __restrict__ W, float* __restrict__ R,
                                                float* __restrict__ rowsq,
                                                double* __restrict__ part, int keep_w) {
   __shared__ double red[256 * 2];
   const int l = L.l;
+  const bool write = R != nullptr;
   double col[kMaxL];
   for (int c = 0; c < kMaxL; ++c) col[c] = 0.0;
   for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < L.n_pad; i += (int64_t)gridDim.x * 256) {
@@ -229,13 +231,15 @@ __global__ __launch_bounds__(256) void k_reset(Layout L, const float* __restrict
     if (i < L.n) {
       for (int c = 0; c < l; ++c) {
         float v = B[i * l + c];
-        R[i * l + c] = v;
-        if (!keep_w) W[i * l + c] = 0.0;
+        if (write) {
+          R[i * l + c] = v;
+          if (!keep_w) W[i * l + c] = 0.0;
+        }
         rs = fmaf(v, v, rs);
         col[c] += (double)v * (double)v;
       }
     }
-    rowsq[i] = rs;
+    if (write) rowsq[i] = rs;
   }
   for (int c = 0; c < l; ++c) {
     red[threadIdx.x] = col[c];
@@ -480,11 +484,18 @@ hipError_t launch_prep(const Layout& L, const Dev& D, const Params& P, const flo
 
 hipError_t launch_reset(const Layout& L, const Dev& D, const float* B, double* W, float* R,
                         bool keep_w, hipStream_t st) {
-  const int groups = 1024;
+  const int groups = kResetGroups;
   hipLaunchKernelGGL(k_reset, dim3(groups), dim3(256), 0, st, L, B, W, R, D.rowsq, D.respart,
                      (int)keep_w);
   hipLaunchKernelGGL(k_reset_final, dim3(1), dim3(64), 0, st, L, D.respart, groups, D.ctl);
   if (L.order == 1) return launch_select(L, D, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_bnorm(const Layout& L, const Dev& D, const float* B, hipStream_t st) {
+  hipLaunchKernelGGL(k_reset, dim3(kResetGroups), dim3(256), 0, st, L, B, nullptr, nullptr,
+                     nullptr, D.respart, 0);
+  hipLaunchKernelGGL(k_reset_final, dim3(1), dim3(64), 0, st, L, D.respart, kResetGroups, D.ctl);
   return hipGetLastError();
 }
 

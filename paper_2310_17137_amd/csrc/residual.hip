@@ -421,14 +421,18 @@ void launch_res(const Layout& L, const Params& P, const ResArgs& a, hipStream_t 
 
 }  // namespace
 
+int residual_groups(int64_t n) {
+  const int tl = res_tiles(n);
+  return (int)((n + 64 * tl - 1) / (64 * tl));
+}
+
 hipError_t launch_residual(const Layout& L, const Dev& D, const Params& P, const float* X,
                            const float* B, const double* W, float* Rout, bool in_place,
                            hipStream_t st) {
   // refining in place keeps the greedy rule's row norms in step with R
   const ResArgs a{X, X, L.n, B, W, Rout, nullptr, in_place ? D.rowsq : nullptr, D.respart};
   launch_res<false>(L, P, a, st);
-  const int tl = res_tiles(L.n);
-  const int groups = (int)((L.n + 64 * tl - 1) / (64 * tl));
+  const int groups = residual_groups(L.n);
   hipLaunchKernelGGL(k_residual_final, dim3(1), dim3(256), 0, st, L, D.respart, groups, D.ctl);
   return hipGetLastError();
 }
