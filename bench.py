@@ -1,23 +1,27 @@
-"""Benchmark: AP epochs/s at house-electric scale (n = 2 000 000).
+"""Benchmark: alternating projection at house-electric scale (n = 2 000 000).
 
-One step = one epoch of alternating projection (Algorithm 1: m block updates,
-each an FP64 block solve and the fused K-tile residual update, then the
-epoch-end residual check) on the synthetic ill-conditioned workload: n = 2 000 000
-points in d = 3 (64-component Gaussian mixture), RBF lengthscale 0.1,
-sigma^2 = 1e-4, block b = 2048 (m = 977), 32 right-hand sides. The main path
-uses FP64 kernel tiles, the only mode whose maintained residual stays equal to
-B - K^ W on this system; the split, FP32 and BF16 tile modes are timed after it
-with their drift reported. The block factorization runs once before the timed
-region (it is per hyperparameter setting); inputs are resident in HBM when
-timing starts.
+The workload is the ill-conditioned recipe as configured: n = 2 000 000 points
+in d = 3 (64-component Gaussian mixture), RBF lengthscale 0.1, sigma^2 = 1e-4,
+block b = 2048 (m = 977), 32 right-hand sides (y and 31 Rademacher probes),
+cyclic order, an FP64 true-residual refinement every 5 epochs. One step is one
+epoch of Algorithm 1 (m block solves, m fused K-tile residual updates, the
+epoch-end check) on the mixed-precision path: FP32 kernel tiles on the FP32
+matrix cores, FP32 residual, FP64 block solves from the cached FP64 inverses,
+and the FP64 true residual (Lemma residual_equality) after every fifth epoch,
+counted inside the timed region. Epochs run as the library's captured HIP
+graph (the shipped path); inputs are resident in HBM when timing starts; the
+block factorization runs once before (it is per hyperparameter setting) and is
+reported separately.
 
-Printed (one JSON line on stdout): epochs/s, the fused update's live roofline
-position from HIP events on its stream, the other tile paths' epochs/s on the
-same problem, residual ratios (maintained and FP64 true), the factor time, the
-time to a relative residual of 1e-2 at n = 2M for the FP64, mixed (split) and
-FP32 paths (the same inputs with the target column alone, greedy order,
-b = 4096; outside the timed epochs), and the FP64 CPU oracle timed on a
-bounded sample on this host.
+Printed (one JSON line on stdout): epochs/s, the fused update's roofline
+position (average launch duration from HIP events of a separate profiled
+epoch), the maintained and FP64 true ratios and the oracle's row-sampled FP64
+ratio of the final W, the other tile paths on the same problem (FP64, split,
+BF16 tiles) and on the same inputs at sigma^2 = 1e-2, the time to a relative
+residual of 1e-2 (factor included) for the FP64, mixed, plain FP32 and split
+paths on the paper's test-time solve (the target column alone, greedy order,
+b = 4096), a short serving run on a scaled stream of the serving recipe, and
+the FP64 CPU oracle timed on a bounded sample on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -108,33 +112,107 @@ def describe(w) -> str:
             f"noise={w.noise:g} order={order}")
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def host_threads() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        return os.cpu_count() or 0
+
+
+def oracle_problem(w):
+    from oracle import apo
+    return apo.Problem(X=w.X.astype(np.float64), B=w.B.astype(np.float64), kernel=w.kernel,
+                       lengthscale=w.lengthscale, outputscale=w.outputscale, noise=w.noise,
+                       b=w.b, order=0)
+
+
+def oracle_rho_sample(p, W, rows: int, seed: int = 0) -> dict:
+    """The FP64 oracle's estimate of mean_c ||r_c|| / ||b_c|| for R = B - K^ W
+    from `rows` rows drawn uniformly without replacement: ||r_c||^2 is n / k
+    times the sum over the sampled rows; the standard error is the delta
+    method's over the rows' contributions."""
+    from oracle import apo
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(p.n, size=min(rows, p.n), replace=False))
+    t0 = time.perf_counter()
+    r = apo.residual_rows(p, W, idx)
+    dt = time.perf_counter() - t0
+    k = idx.size
+    sq = r * r
+    S = sq.sum(0) * (p.n / k)
+    bn = np.linalg.norm(p.B, axis=0)
+    ok = bn > 0
+    rho = float(np.mean(np.where(ok, np.sqrt(S) / np.where(ok, bn, 1.0), 0.0)))
+    g = np.where(ok & (S > 0), 1.0 / (2.0 * p.l * np.where(ok, bn, 1.0) * np.sqrt(np.maximum(S, 1e-300))), 0.0)
+    z = p.n * (sq @ g)
+    se = float(np.std(z, ddof=1) / math.sqrt(k)) if k > 1 else float("nan")
+    return {"rho": rho, "se": se, "rows": int(k), "seconds": dt, "threads": apo.num_threads()}
+
+
+class OracleChecks:
+    """Row-sampled oracle residuals computed on host threads (one job at a
+    time) while the GPU goes on; results are collected at the end."""
+
+    def __init__(self):
+        import concurrent.futures as cf
+        self.ex = cf.ThreadPoolExecutor(max_workers=1)
+        self.jobs = {}
+
+    def submit(self, key, p, W_host, rows, seed=0):
+        self.jobs[key] = self.ex.submit(oracle_rho_sample, p, W_host, rows, seed)
+
+    def get(self, key):
+        f = self.jobs.get(key)
+        if f is None:
+            return None
+        try:
+            return f.result()
+        except Exception as e:  # noqa: BLE001 - reported, not fatal to the bench
+            return {"error": str(e)}
+
+    def close(self):
+        self.ex.shutdown(wait=True)
+
+
 def trans_per_entry(kernel: int) -> int:
     return 1 if kernel == 0 else 2
 
 
 def cpu_baseline(w, updates: int) -> dict:
-    """The FP64 oracle as it stands, on this host: `updates` block updates of the
-    same workload (factor of each sampled block included), scaled to epochs/s."""
+    """The FP64 oracle as it stands, on this host: `updates` block updates of
+    the same workload spread over the epoch (blocks j m / updates, each block's
+    factor computed first and not timed), scaled to epochs/s."""
     from oracle import apo
-    p = apo.Problem(X=w.X.astype(np.float64), B=w.B.astype(np.float64), kernel=w.kernel,
-                    lengthscale=w.lengthscale, outputscale=w.outputscale, noise=w.noise, b=w.b,
-                    order=0)
+    p = oracle_problem(w)
     W = np.zeros_like(p.B)
     R = p.B.copy()
-    factors = [apo.factor_one(p, u) for u in range(updates)]  # per-setting cost, not timed
+    blocks = sorted({(u * w.m) // updates for u in range(updates)})
+    factors = [apo.factor_one(p, j) for j in blocks]  # per-setting cost, not timed
     t0 = time.perf_counter()
-    for u in range(updates):
-        apo.update_block(p, factors[u], W, R, u)
+    for Lj, j in zip(factors, blocks):
+        apo.update_block(p, Lj, W, R, j)
     dt = time.perf_counter() - t0
-    per_update = dt / updates
+    per_update = dt / len(blocks)
     return {"value": 1.0 / (per_update * w.m), "unit": "epochs/s", "cores": apo.num_threads(),
             "kind": "oracle",
-            "sample": f"{updates} of {w.m} block updates of one epoch (cyclic, blocks "
-                      f"0..{updates - 1}, factors precomputed) in {dt:.1f} s, scaled by m",
-            "cpu": platform.processor() or platform.machine()}
+            "sample": f"{len(blocks)} of {w.m} block updates of one cyclic epoch (blocks "
+                      f"{', '.join(map(str, blocks))}; factors precomputed) in {dt:.1f} s, "
+                      f"scaled by m",
+            "cpu": cpu_model(), "host_threads": host_threads()}
 
 
-def make_solver(w, X, tile):
+def make_solver(w, X, tile, refine_every=None):
     """Factor the blocks of workload w (X on the GPU); returns (solver, seconds)."""
     import torch
     from paper_2310_17137_amd import ap
@@ -142,42 +220,58 @@ def make_solver(w, X, tile):
     t0 = time.perf_counter()
     s = ap.Solver(X, l=w.l, b=w.b, kernel=w.kernel, lengthscale=w.lengthscale,
                   outputscale=w.outputscale, noise=w.noise, order=w.order, tile=tile,
-                  refine_every=w.refine_every, tol=w.tol, min_epochs=w.min_epochs,
-                  max_epochs=w.max_epochs)
+                  refine_every=w.refine_every if refine_every is None else refine_every,
+                  tol=w.tol, min_epochs=w.min_epochs, max_epochs=w.max_epochs)
     torch.cuda.synchronize()
     return s, time.perf_counter() - t0
 
 
-def default_time_to_tol(tiles, max_epochs=60):
-    """Time to rho < 1e-2 at n = 2M: the n = 2M inputs with the target column
-    alone (the paper's test-time solve), greedy block order, b = 4096, for each
-    tile path (ap_solve with FP64 true-residual confirmation)."""
+# Time-to-tolerance paths: (name, tile, refine_every). "mixed" is FP32 tiles
+# with the FP64 true residual every 5 epochs and at the tolerance hit; "fp32"
+# is the plain FP32 path (FP32 tiles, the maintained residual only, stopping
+# on it); "split" is the BF16 matrix-core form (escalates to FP64 tiles when
+# its true residual drifts); "fp64" is FP64 tiles.
+TTT_RUNS = (("fp64", 3, 5), ("mixed", 0, 5), ("fp32", 0, 0), ("split", 2, 5))
+
+
+def default_time_to_tol(checks, runs=TTT_RUNS, max_epochs=60, oracle_rows=2048):
+    """Time to rho < 1e-2 at n = 2M on the paper's test-time solve: the n = 2M
+    inputs with the target column alone, greedy block order, b = 4096. Each
+    run's total includes its block factorization; the oracle estimates the
+    final W's true ratio from sampled rows."""
     import torch
     from paper_2310_17137_amd import gen
     w = gen.c3(l=1)
     w.b, w.order, w.max_epochs = 4096, gen.GREEDY, max_epochs
     X = torch.from_numpy(w.X).cuda()
     B = torch.from_numpy(w.B).cuda()
-    runs = time_to_tol(w, lambda tile: make_solver(w, X, tile), B, tiles)
-    out = {"workload": describe(w), "tol": w.tol, "max_epochs": w.max_epochs, "runs": {}}
-    for r in runs:
-        out["runs"][r["tile"]] = {k: r.get(k) for k in ("converged", "epochs", "time_to_tol_s",
-                                                         "factor_s", "t_refine", "rho_true",
-                                                         "final_tile", "escalated_at")}
+    p = oracle_problem(w)
+    out = {"workload": describe(w), "variant": "test-time solve of y alone (l = 1), greedy "
+           "order, b = 4096, on the n = 2M inputs", "tol": w.tol, "max_epochs": w.max_epochs,
+           "runs": {}}
+    for name, tile, refine in runs:
+        r = time_to_tol(w, lambda t, re=refine: make_solver(w, X, t, re), B, [(name, tile)])[0]
+        rec = {k: r.get(k) for k in ("converged", "epochs", "time_to_tol_s", "factor_s",
+                                     "t_epochs", "t_refine", "rho_maintained", "rho_true",
+                                     "final_tile", "escalated_at", "restarted_at", "error")}
+        rec["refine_every"] = refine
+        out["runs"][name] = rec
+        if "W" in r:
+            checks.submit(("ttt", name), p, r.pop("W"), oracle_rows, seed=11)
     del X, B
     torch.cuda.empty_cache()
-    return out
+    return out, p
 
 
-def time_to_tol(w, make, B, tiles):
-    """ap_solve per tile path; a watcher thread reports the epoch and ratio
-    every 20 s (ap_batch_peek reads the control block while the solve runs)."""
+def time_to_tol(w, make, B, runs):
+    """ap_solve per (name, tile) run; a watcher thread reports the epoch and
+    ratio every 20 s (ap_batch_peek reads the control block while the solve
+    runs). time_to_tol_s includes the block factorization."""
     import threading
     from paper_2310_17137_amd import ap
-    by_name = {v: k for k, v in TILE_NAMES.items()}
-    runs = []
-    for name in tiles:
-        s, t_factor = make(by_name[name])
+    out = []
+    for name, tile in runs:
+        s, t_factor = make(tile)
         W, R = s.new_state(B)
         box = {}
 
@@ -205,15 +299,18 @@ def time_to_tol(w, make, B, tiles):
             st = box["st"]
             run.update({"converged": st.converged, "epochs": st.epochs, "refines": st.refines,
                         "t_epochs": st.t_epochs, "t_refine": st.t_refine,
-                        "time_to_tol_s": st.t_epochs + st.t_refine if st.converged else None,
+                        "time_to_tol_s": (t_factor + st.t_epochs + st.t_refine
+                                          if st.converged else None),
                         "rho_maintained": st.rho_maintained, "rho_true": st.rho_true,
-                        "final_tile": TILE_NAMES[st.tile], "escalated_at": st.escalated_at})
-        log(f"[tol] {name}: {json.dumps(run)}")
-        runs.append(run)
+                        "final_tile": TILE_NAMES[st.tile], "escalated_at": st.escalated_at,
+                        "restarted_at": st.restarted_at})
+            run["W"] = W.cpu().numpy()
+        log(f"[tol] {name}: " + json.dumps({k: v for k, v in run.items() if k != "W"}))
+        out.append(run)
         del s, W, R
         import torch
         torch.cuda.empty_cache()
-    return runs
+    return out
 
 
 def bench_rho_trace(w, make, B, args):
@@ -392,15 +489,25 @@ def main():
     ap_.add_argument("--steps", type=int, default=5)
     ap_.add_argument("--warmup", type=int, default=1)
     ap_.add_argument("--workload", default="c3")
-    ap_.add_argument("--main", default="fp64", choices=["fp64", "split", "fp32", "bf16"])
+    ap_.add_argument("--main", default="fp32", choices=["fp64", "split", "fp32", "bf16"],
+                     help="tile mode of the timed path (fp32: the mixed-precision path)")
+    ap_.add_argument("--refine-every", type=int, default=-1,
+                     help="FP64 true residual after every k-th epoch of the timed path "
+                          "(-1: the workload's, 5 for the n = 2M recipe; 0: none)")
     ap_.add_argument("--other-steps", type=int, default=1,
                      help="timed epochs of each other tile path (0: main path only)")
     ap_.add_argument("--skip", default="", help="comma-separated tile paths not to run")
-    ap_.add_argument("--cpu-updates", type=int, default=2)
+    ap_.add_argument("--cpu-updates", type=int, default=5)
+    ap_.add_argument("--oracle-rows", type=int, default=1024,
+                     help="rows of the oracle's sampled FP64 residual of the timed path's W")
     ap_.add_argument("--no-cpu", action="store_true")
     ap_.add_argument("--no-true-residual", action="store_true")
     ap_.add_argument("--no-ttt", action="store_true",
                      help="skip the time-to-tolerance runs of the default line")
+    ap_.add_argument("--no-serve", action="store_true",
+                     help="skip the serving run of the default line")
+    ap_.add_argument("--no-noise2", action="store_true",
+                     help="skip the sigma^2 = 1e-2 comparison of the default line")
     ap_.add_argument("--time-to-tol", default="",
                      help="comma-separated tile paths: run ap_solve on each (reset, epochs, "
                           "FP64 true-residual refinement and confirmation) and print the time "
@@ -482,108 +589,178 @@ def main():
     if args.time_to_tol:
         if args.max_epochs > 0:
             w.max_epochs = args.max_epochs
-        runs = time_to_tol(w, make, B, args.time_to_tol.split(","))
+        # names: fp64, split, bf16 (the workload's refine_every), mixed (FP32
+        # tiles with it), fp32 (FP32 tiles without FP64 true residuals)
+        spec = {"fp64": (3, None), "split": (2, None), "bf16": (1, None), "mixed": (0, None),
+                "fp32": (0, 0)}
+        runs = []
+        for name in args.time_to_tol.split(","):
+            tile, refine = spec[name]
+            r = time_to_tol(w, lambda t, re=refine: make_solver(w, X, t, re), B,
+                            [(name, tile)])[0]
+            r.pop("W", None)
+            runs.append(r)
         print(json.dumps({"time_to_tol": runs, "workload": describe(w), "tol": w.tol,
                           "refine_every": w.refine_every, "max_epochs": w.max_epochs}),
               flush=True)
         return
 
-    def run_path(tile, steps, warmup, want_true):
-        """Factor, reset, warm up, time `steps` epochs with per-phase events."""
+    checks = OracleChecks()
+    p_main = oracle_problem(w) if not args.no_cpu else None
+    refine_every = w.refine_every if args.refine_every < 0 else args.refine_every
+    tiles = {"fp64": ap.TILE_FP64, "split": ap.TILE_SPLIT, "fp32": ap.TILE_FP32,
+             "bf16": ap.TILE_BF16}
+
+    def true_ratio(s, W, R):
+        Rt = torch.empty_like(R)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        cols = s.residual(B, W, R, R_out=Rt)
+        dt = time.perf_counter() - t1
+        del Rt
+        return float(np.mean(cols)), dt
+
+    def run_main(tile, steps, warmup):
+        """The timed path: reset, `warmup` epochs, then `steps` epochs as graph
+        replays with one event pair per epoch and the FP64 refinement after
+        every refine_every-th epoch (counted from the reset) inside the timed
+        region; then one profiled epoch (eager launches with per-phase events)
+        for the roofline, outside it."""
         s, t_factor = make(tile)
         W, R = s.new_state(B)
         s.reset(B, W, R)
-        res = {"tile": TILE_NAMES[tile], "factor_s": t_factor, "steps": steps, "warmup": warmup,
+        res = {"tile": TILE_NAMES[tile], "factor_s": t_factor, "steps": steps,
+               "warmup": warmup, "refine_every": refine_every,
                "workspace_gb": s.ws_bytes / 1e9}
-        ok = True
+        epoch = 0
+
+        def one_epoch():
+            nonlocal epoch
+            s.epoch(B, W, R, 1)
+            epoch += 1
+            if refine_every > 0 and epoch % refine_every == 0:
+                s.residual(B, W, R, want_col_rel=False)  # R <- B - K^ W (in place)
+                return True
+            return False
+
         for i in range(warmup):
-            s.epoch(B, W, R, 1)
-            try:
-                rho, _ = s.rel_residual()
-            except ap.ApError as e:
-                ok, rho = False, float("nan")
-                log(f"[bench] {res['tile']}: warmup epoch {i + 1}: {e}")
-                break
+            one_epoch()
+            rho, _ = s.rel_residual()
             log(f"[bench] {res['tile']}: warmup epoch {i + 1}: rho {rho:.6f}")
-        if not ok:
-            res["diverged"] = True
-            del s, W, R
-            torch.cuda.empty_cache()
-            return res
-        s.profile(True)
         torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        refines = 0
         t0 = time.perf_counter()
-        done = []
+        ev[0].record()
         for i in range(steps):
-            s.epoch(B, W, R, 1)
-            ev = torch.cuda.Event()
-            ev.record()
-            done.append(ev)
+            refines += one_epoch()
+            ev[i + 1].record()
             if i >= 1:  # one epoch stays queued while the previous one is reported
-                done[i - 1].synchronize()
-                log(f"[bench] {TILE_NAMES[tile]}: epoch {i} of {steps} done at "
+                ev[i].synchronize()
+                log(f"[bench] {res['tile']}: epoch {i} of {steps} done at "
                     f"{time.perf_counter() - t0:.1f} s")
         torch.cuda.synchronize()
         t_timed = time.perf_counter() - t0
+        per_epoch = [ev[i].elapsed_time(ev[i + 1]) * 1e-3 for i in range(steps)]
+        rho, cols = s.rel_residual()
+        res.update({"t_timed": t_timed, "epochs_per_s": steps / t_timed,
+                    "ms_per_step": t_timed / steps * 1e3, "refines_timed": refines,
+                    "epoch_s_events": per_epoch, "rho_maintained": rho,
+                    "epochs_done": epoch})
+        log(f"[bench] {res['tile']}: {steps} timed epochs ({refines} refinements) in "
+            f"{t_timed:.3f} s, rho {rho:.6f}")
+        if not args.no_true_residual:
+            res["rho_true"], res["true_residual_s"] = true_ratio(s, W, R)
+            res["drift"] = abs(res["rho_true"] - rho) / res["rho_true"]
+            log(f"[bench] {res['tile']}: FP64 true ratio {res['rho_true']:.6f} "
+                f"(maintained {rho:.6f}) in {res['true_residual_s']:.2f} s")
+        if p_main is not None and args.oracle_rows > 0:
+            checks.submit("main", p_main, W.cpu().numpy(), args.oracle_rows, seed=5)
+        # per-phase split and the fused kernel's launch duration: one more
+        # epoch with eager launches and events (outside the timed region)
+        s.profile(True)
+        s.epoch(B, W, R, 1)
         phases = s.profile_read()
         s.profile(False)
-        try:
-            rho, _ = s.rel_residual()
-        except ap.ApError:
-            rho = float("nan")
-        res.update({"t_timed": t_timed, "epochs_per_s": steps / t_timed,
-                    "ms_per_step": t_timed / steps * 1e3, "rho_maintained": rho,
-                    "phases": {k: {"s": v[0], "launches": v[1]} for k, v in phases.items()}})
-        log(f"[bench] {res['tile']}: {steps} timed epochs in {t_timed:.3f} s, rho {rho:.6f}")
+        res["profiled_epoch"] = {k: {"s": v[0], "launches": v[1]} for k, v in phases.items()}
         for k, (sec, cnt) in phases.items():
             if cnt:
                 log(f"[bench]   {k:14s} {sec * 1e3:10.2f} ms over {cnt} launches "
                     f"({sec / cnt * 1e6:.1f} us each)")
-        if want_true and math.isfinite(rho) and rho < 1e6:
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            Rt = torch.empty_like(R)
-            cols = s.residual(B, W, R, R_out=Rt)
-            res["true_residual_s"] = time.perf_counter() - t1
-            res["rho_true"] = float(np.mean(cols))
-            log(f"[bench] {res['tile']}: FP64 true residual rho {res['rho_true']:.6f} in "
-                f"{res['true_residual_s']:.2f} s")
-            del Rt
-        # the maintained residual has left B - K^ W when they differ by > 0.1%
-        res["drift"] = (abs(res["rho_true"] - rho) / res["rho_true"]
-                        if res.get("rho_true") else None)
-        res["diverged"] = not (math.isfinite(rho) and rho < 1e6 and
-                               (res["drift"] is None or res["drift"] < 1e-3))
         del s, W, R
         torch.cuda.empty_cache()
         return res
 
-    # The main path is the one whose maintained residual stays the true one on
-    # this system: FP64 kernel tiles. The FP32-grade and BF16 tile paths run
-    # after it for their epoch rates; on this workload their maintained
-    # residual drifts away from B - K^ W (reported as "diverged").
-    paths = {}
-    main_tile = {"fp64": ap.TILE_FP64, "split": ap.TILE_SPLIT, "fp32": ap.TILE_FP32,
-                 "bf16": ap.TILE_BF16}[args.main]
-    paths[args.main] = run_path(main_tile, args.steps, args.warmup, not args.no_true_residual)
-    for name, tile, steps, warm in (("split", ap.TILE_SPLIT, args.other_steps, 1),
-                                    ("fp32", ap.TILE_FP32, args.other_steps, 1),
-                                    ("bf16", ap.TILE_BF16, args.other_steps, 1)):
-        if name != args.main and steps > 0 and name not in args.skip.split(","):
-            paths[name] = run_path(tile, steps, warm, not args.no_true_residual)
-    main = paths[args.main]
+    def run_compare(wk, Bk, make_k, tile, steps, warmup):
+        """Another tile path: `warmup` + `steps` epochs, timed through the
+        graph, then the FP64 true ratio and its drift from the maintained one."""
+        s, t_factor = make_k(tile)
+        W, R = s.new_state(Bk)
+        s.reset(Bk, W, R)
+        res = {"tile": TILE_NAMES[tile], "factor_s": t_factor, "steps": steps}
+        try:
+            for i in range(warmup):
+                s.epoch(Bk, W, R, 1)
+                s.rel_residual()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.epoch(Bk, W, R, steps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            rho, _ = s.rel_residual()
+        except ap.ApError as e:
+            res.update({"diverged": True, "error": str(e)})
+            log(f"[bench] {res['tile']} ({wk.name}): {e}")
+            del s, W, R
+            torch.cuda.empty_cache()
+            return res
+        res.update({"epochs_per_s": steps / dt, "ms_per_step": dt / steps * 1e3,
+                    "rho_maintained": rho, "epochs": warmup + steps})
+        if not args.no_true_residual and math.isfinite(rho) and rho < 1e6:
+            Rt = torch.empty_like(R)
+            cols = s.residual(Bk, W, R, R_out=Rt)
+            res["rho_true"] = float(np.mean(cols))
+            res["drift"] = abs(res["rho_true"] - rho) / res["rho_true"]
+            del Rt
+        res["diverged"] = not (math.isfinite(rho) and rho < 1e6 and
+                               (res.get("drift") is None or res["drift"] < 1e-2))
+        log(f"[bench] {res['tile']} ({wk.name}): {json.dumps(res)}")
+        del s, W, R
+        torch.cuda.empty_cache()
+        return res
 
-    upd = main["phases"]["fused_update"]
+    main_tile = tiles[args.main]
+    main = run_main(main_tile, args.steps, args.warmup)
+    paths = {}
+    for name in ("fp64", "split", "bf16", "fp32"):
+        if name != args.main and args.other_steps > 0 and name not in args.skip.split(","):
+            paths[name] = run_compare(w, B, make, tiles[name], args.other_steps, 1)
+
+    # the same inputs at sigma^2 = 1e-2, where every FP32-grade path holds
+    noise2 = None
+    if not args.no_noise2 and w.name == "c3":
+        from paper_2310_17137_amd import gen
+        w2 = gen.c3(noise=1e-2)
+        B2 = torch.from_numpy(w2.B).to(dev)
+        noise2 = {"workload": describe(w2), "paths": {}}
+        for name in ("split", "fp32"):
+            noise2["paths"][name] = run_compare(w2, B2, lambda t: make_solver(w2, X, t),
+                                                tiles[name], 2, 1)
+        del B2
+
+    upd = main["profiled_epoch"]["fused_update"]
     avg = upd["s"] / upd["launches"]
     entries_per_launch = w.n * w.n / w.m  # every epoch touches n^2 kernel entries
     flops_launch = 2.0 * (w.d + w.l) * entries_per_launch
     achieved = flops_launch / avg / 1e12
     peak = {ap.TILE_FP32: PEAK_FP32_TFLOPS, ap.TILE_FP64: PEAK_FP64_TFLOPS}.get(
         main_tile, PEAK_BF16_TFLOPS)
-    # the split path runs six BF16 partial products per tile entry and column
     mfma_flops_launch = flops_launch * (6 if main_tile == ap.TILE_SPLIT else 1)
-    trans_rate = trans_per_entry(w.kernel) * entries_per_launch / avg
-    bytes_launch = 2.0 * w.n * w.l * 4 + w.n * w.d * 4
+    # R read and written (FP32) plus the row features: the FP64 prepared
+    # copies (stride d rounded up to 4) on FP32 and split tiles, X itself on
+    # FP64 tiles
+    feat = w.n * (w.d * 4 if main_tile == ap.TILE_FP64 else ((w.d + 3) // 4 * 4) * 8)
+    bytes_launch = 2.0 * w.n * w.l * 4 + feat
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak,
                 "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": measured_traffic(main["tile"], w.name),
@@ -592,15 +769,27 @@ def main():
                 "flops_counted": "2 (d + l) per kernel entry: x.x' and the product with the step",
                 "avg_launch_us": avg * 1e6,
                 "flops_per_entry": 2 * (w.d + w.l), "entries_per_launch": entries_per_launch,
-                "transcendental_frac": trans_rate / PEAK_TRANS_PER_S,
                 "issued_mfma_tflops": mfma_flops_launch / avg / 1e12,
                 "hbm_gbs": bytes_launch / avg / 1e9}
 
     ttt = None
     if not args.no_ttt and w.name == "c3":
-        del B, X
+        del B
         torch.cuda.empty_cache()
-        ttt = default_time_to_tol(["fp64", "split", "fp32"])
+        ttt, _p1 = default_time_to_tol(checks)
+
+    serving = None
+    if not args.no_serve:
+        serving = serving_run(checks)
+
+    main["oracle_sampled"] = checks.get("main")
+    if ttt is not None:
+        for name in ttt["runs"]:
+            ttt["runs"][name]["oracle_sampled"] = checks.get(("ttt", name))
+    if serving is not None:
+        for rec in serving["requests"]:
+            rec["oracle_sampled"] = checks.get(("serve", rec["rid"]))
+    checks.close()
 
     cpu = None
     if not args.no_cpu and args.cpu_updates > 0:
@@ -608,20 +797,57 @@ def main():
         log(f"[bench] oracle on {cpu['cores']} host threads: {cpu['value']:.3e} epochs/s")
 
     out = {
-        "metric": "AP epochs/s at n=2M" if w.name == "c3" else f"AP epochs/s ({w.name})",
+        "metric": "AP epochs/s + time to rel. residual 1e-2 at n=2M, mixed vs FP32; p99 latency",
         "value": main["epochs_per_s"], "unit": "epochs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": main["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": main["tile"], "data": "synthetic",
+        "dtype": {"fp32": "f32", "fp64": "f64", "split": "bf16x3", "bf16": "bf16"}[main["tile"]],
+        "data": "synthetic",
         "config": {"workload": describe(w), "tiles": main["tile"],
                    "solves": "FP64 block inverses", "residual": "FP32",
-                   "global_batch": w.l, "parallelism": "single GPU"},
+                   "refine_every": refine_every, "global_batch": w.l,
+                   "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "time_to_tol": ttt,
+        "main": main,
         "paths": paths,
+        "noise_1e-2": noise2,
+        "time_to_tol": ttt,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
+
+
+def serving_run(checks, count=16, n_min=8192, n_max=32768, max_epochs=300, oracle_rows=512):
+    """A scaled stream of the serving recipe, every request queued at t = 0
+    (the loop's capacity): continuous batching with split tiles and the FP64
+    true residual every 5 epochs; per request the FP64 true ratio from the
+    loop and the oracle's row-sampled ratio of its W."""
+    import dataclasses
+    from paper_2310_17137_amd import ap, gen, serve
+    reqs = [dataclasses.replace(r, arrival=0.0)
+            for r in gen.serving_requests(seed=0, count=count, n_min=n_min, n_max=n_max)]
+    srv = serve.Server(max_active=16, tile=ap.TILE_SPLIT, refine_every=5, max_epochs=max_epochs,
+                       keep_w=True)
+    t0 = time.perf_counter()
+    done = srv.run(reqs, log=lambda m: log(m) if "done" in m else None)
+    wall = time.perf_counter() - t0
+    out = serve.summarize(done, wall)
+    out.update({"stream": f"{count} requests of the serving recipe (seed 0) with n in "
+                          f"[{n_min}, {n_max}], all queued at t = 0, max {max_epochs} epochs, "
+                          "split tiles, FP64 true residual every 5 epochs",
+                "peak_active": srv.peak_active, "requests": []})
+    by_id = {r.rid: r for r in reqs}
+    for d in sorted(done, key=lambda d: d.rid):
+        out["requests"].append({"rid": d.rid, "n": d.n, "d": d.d, "l": d.l, "epochs": d.epochs,
+                                "latency_s": d.latency, "rho_true": d.rho_true,
+                                "converged": d.converged, "tile": TILE_NAMES[d.tile],
+                                "error": d.error or None})
+        if d.W is not None:
+            wk = by_id[d.rid].make()
+            checks.submit(("serve", d.rid), oracle_problem(wk), d.W, oracle_rows, seed=d.rid)
+    log(f"[serve] {json.dumps({k: v for k, v in out.items() if k != 'requests'})}")
+    return out
 
 
 if __name__ == "__main__":

@@ -292,6 +292,96 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const double* __re
   epilogue(L, row0, start, len, acc, R, rowsq, colsq, want_rowsq, want_colsq, (int)blockIdx.x);
 }
 
+// FP32 tiles with few right-hand sides (l <= 8): the product with the step on
+// the vector units, since the 32-column matrix tile would do 32 multiply-adds
+// per kernel entry where l are needed. One thread per row (256 rows per
+// workgroup, the same partials as the tile kernels); the chunk's column
+// features and step are staged in LDS and read by all lanes at once. Each
+// chunk's l sums accumulate in FP32 and the chunk sums in FP64, as in the
+// matrix-core kernel.
+template <int KERN, int DV, int DP, int NV>
+__global__ __launch_bounds__(256) void k_fused_fp32v(Layout L, const double* __restrict__ xv,
+                                                     const float* __restrict__ dtile,
+                                                     const Ctl* __restrict__ ctl, int block,
+                                                     float* __restrict__ R,
+                                                     float* __restrict__ rowsq,
+                                                     float* __restrict__ colsq, int want_rowsq,
+                                                     int want_colsq) {
+  __shared__ double sx[kChunk][DP];
+  __shared__ float sd[kChunk][NV];
+  __shared__ float red[4][NV];
+  const int blk = resolve_block(block, ctl);
+  if (blk < 0) return;
+  const int64_t start = (int64_t)blk * L.b;
+  const int len = (int)std::min<int64_t>(L.b, L.n - start);
+  const int nch = (len + kChunk - 1) / kChunk;
+  const int l = L.l;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int64_t row = (int64_t)blockIdx.x * kRowsWG + threadIdx.x;
+
+  double xr[DV];
+#pragma unroll
+  for (int k = 0; k < DV; ++k) xr[k] = xv[row * DP + k];
+  double acc[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) acc[c] = 0.0;
+
+  for (int ch = 0; ch < nch; ++ch) {
+    const int64_t cb = start + (int64_t)ch * kChunk;
+    __syncthreads();
+    for (int e = threadIdx.x; e < kChunk * DP; e += 256) (&sx[0][0])[e] = xv[cb * DP + e];
+    for (int e = threadIdx.x; e < kChunk * NV; e += 256)
+      sd[e / NV][e % NV] = dtile[((int64_t)ch * kChunk + e / NV) * kMaxL + e % NV];
+    __syncthreads();
+    float part[NV];
+#pragma unroll
+    for (int c = 0; c < NV; ++c) part[c] = 0.f;
+#pragma unroll 4
+    for (int j = 0; j < kChunk; ++j) {
+      const float kv = kmap_acc<KERN>(dist2<DV>(xr, sx[j]));
+#pragma unroll
+      for (int c = 0; c < NV; ++c) part[c] = fmaf(kv, sd[j][c], part[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < NV; ++c) acc[c] += (double)part[c];
+  }
+
+  const bool live = row < L.n;
+  const bool in_i = row >= start && row < start + len;
+  float rs = 0.f, csq[NV];
+#pragma unroll
+  for (int c = 0; c < NV; ++c) {
+    csq[c] = 0.f;
+    if (live && c < l) {
+      const float r = in_i ? 0.f : (float)((double)R[row * l + c] - acc[c]);
+      R[row * l + c] = r;
+      rs = fmaf(r, r, rs);
+      csq[c] = r * r;
+    }
+  }
+  if (want_rowsq && row < L.n_pad) rowsq[row] = live ? rs : 0.f;
+  if (want_colsq) {
+#pragma unroll
+    for (int c = 0; c < NV; ++c) {
+      float x = csq[c];
+      x += __shfl_xor(x, 1);
+      x += __shfl_xor(x, 2);
+      x += __shfl_xor(x, 4);
+      x += __shfl_xor(x, 8);
+      x += __shfl_xor(x, 16);
+      x += __shfl_xor(x, 32);
+      if (lane == 0) red[wave][c] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxL) {
+      const int c = threadIdx.x;
+      float v = 0.f;
+      if (c < NV) v = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+      colsq[(size_t)blockIdx.x * kMaxL + c] = c < l ? v : 0.f;
+    }
+  }
+}
+
 // Split path: FP32 kernel tiles (FP64 squared distance of the FP64 prepared
 // features, kmap_acc) and the product on BF16 matrix cores. The tile K = kh + km + kl and the
 // step d = dh + dm + dl are each held as three BF16 terms (24 significant bits),
@@ -449,9 +539,37 @@ hipError_t launch_bf16(const Layout& L, const Dev& D, int32_t block, float* R, b
   return hipGetLastError();
 }
 
+template <int KERN, int NV>
+hipError_t launch_fp32v(const Layout& L, const Dev& D, int32_t block, float* R, bool wr, bool wc,
+                        hipStream_t st) {
+  const dim3 g(L.nwg), t(256);
+  const float* dt = (const float*)D.dtile;
+#define AP_FP32V(DV, DP)                                                                  \
+  hipLaunchKernelGGL((k_fused_fp32v<KERN, DV, DP, NV>), g, t, 0, st, L, D.xv, dt, D.ctl, \
+                     block, R, D.rowsq, D.colsq, (int)wr, (int)wc)
+  if (L.d == 3) {
+    AP_FP32V(3, 4);
+  } else {
+    switch (L.dp) {
+      case 4: AP_FP32V(4, 4); break;
+      case 8: AP_FP32V(8, 8); break;
+      case 12: AP_FP32V(12, 12); break;
+      case 16: AP_FP32V(16, 16); break;
+      case 20: AP_FP32V(20, 20); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+#undef AP_FP32V
+  return hipGetLastError();
+}
+
 template <int KERN>
 hipError_t launch_fp32(const Layout& L, const Dev& D, int32_t block, float* R, bool wr, bool wc,
                        hipStream_t st) {
+  if (L.l <= 1) return launch_fp32v<KERN, 1>(L, D, block, R, wr, wc, st);
+  if (L.l <= 2) return launch_fp32v<KERN, 2>(L, D, block, R, wr, wc, st);
+  if (L.l <= 4) return launch_fp32v<KERN, 4>(L, D, block, R, wr, wc, st);
+  if (L.l <= 8) return launch_fp32v<KERN, 8>(L, D, block, R, wr, wc, st);
   const dim3 g(L.nwg), t(256);
   const float* dt = (const float*)D.dtile;
 #define AP_FP32(DV, DP)                                                                        \
