@@ -59,7 +59,17 @@ MEASURED_TRAFFIC = {
     ("fp64", "c3"): {
         "bytes": 138812.4 * 1024 * 2.0 + 250001.0 * 1024 * 1.0,
         "files": ("update64.hip", "kmap64.h", "ap_internal.h"),
-        "sha256": "33d736bdab08eb1b996bc37c859d97f83604c96ae1d2482aba733aa364ae0937",
+        "sha256": "512db27ea605542cdc0f0c033b35f149289d882ae3af47f1ef9320e37648885f",
+    },
+    ("fp32", "c3"): {
+        "bytes": 157433.0 * 1024 * 2.0 + 250001.0 * 1024 * 1.0,
+        "files": ("update.hip", "ap_internal.h"),
+        "sha256": "aafe05f3711e0abc8ca95122419561b110bb5335acd1674f441de77ccf84905e",
+    },
+    ("split", "c3"): {
+        "bytes": 157975.0 * 1024 * 2.0 + 250001.0 * 1024 * 1.0,
+        "files": ("update.hip", "ap_internal.h"),
+        "sha256": "aafe05f3711e0abc8ca95122419561b110bb5335acd1674f441de77ccf84905e",
     },
 }
 
