@@ -41,21 +41,72 @@ def knorm2(E: np.ndarray, K: np.ndarray) -> float:
     return float(np.sum(E * (K @ E)))
 
 
-def fp32_tile_floor(p, epochs: int) -> list[float]:
-    """Per-epoch relative distance (Frobenius) between the FP64 oracle's cyclic
-    iterates and those of a perfect FP32-tile implementation of the same
-    updates: every kernel value K^_ij rounded once to FP32, the step s delta
-    rounded to FP32, the products of each 32-column chunk accumulated in FP32
-    (numpy's FP32 matrix product), the chunk sums in FP64, and R stored in
-    FP32 after each update; block solves and W in FP64. It is the rounding
-    floor the GPU's FP32-grade tiles are judged against: their arithmetic
-    differs only in the order of the FP32 sums and in kernel values within
-    about 2 ulp instead of half an ulp."""
+def bf16(x) -> np.ndarray:
+    """Round to the nearest bfloat16 (ties to even), returned as float32."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000).astype(np.uint32)
+    return u.view(np.float32)
+
+
+_FLOOR_LIB = None
+
+
+def _floor_lib():
+    """tests/tile_floor.c, compiled on first use (gcc, OpenMP) next to it."""
+    global _FLOOR_LIB
+    if _FLOOR_LIB is None:
+        import ctypes
+        import os
+        import subprocess
+        here = os.path.dirname(os.path.abspath(__file__))
+        src = os.path.join(here, "tile_floor.c")
+        lib = os.path.join(here, "_tile_floor.so")
+        if not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+            subprocess.run(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-o", lib + ".tmp", src],
+                           check=True)
+            os.replace(lib + ".tmp", lib)
+        L = ctypes.CDLL(lib)
+        P = ctypes.c_void_p
+        L.chunk_products.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                     ctypes.c_int, P]
+        L.chunk_products.restype = None
+        _FLOOR_LIB = L
+    return _FLOOR_LIB
+
+
+def _chunk_products(Kt, dt, group: int) -> np.ndarray:
+    """Sum_q Kt[:, q] dt[q] over a block as the matrix cores form it (see
+    tests/tile_floor.c). Kt (n x len) and dt (len x l) hold the rounded
+    operands (float32)."""
+    Kt = np.ascontiguousarray(Kt, dtype=np.float32)
+    dt = np.ascontiguousarray(dt, dtype=np.float32)
+    n, ln = Kt.shape
+    l = dt.shape[1]
+    out = np.empty((n, l))
+    _floor_lib().chunk_products(Kt.ctypes.data, dt.ctypes.data, n, ln, l, group,
+                                out.ctypes.data)
+    return out
+
+
+def tile_trajectory(p, epochs: int, mode: str = "fp32", log=None):
+    """Cyclic epochs of the FP64 oracle beside a perfect reduced-precision
+    tile implementation of the same updates. Returns, per epoch, the oracle's
+    W and the relative distance (Frobenius) of the emulated run's W from it:
+    the rounding floor the GPU's tiles are judged against.
+
+    mode "fp32": every kernel value K^_ij rounded once to FP32 and the step
+    s delta rounded to FP32; each 32-column chunk summed on an FP32
+    accumulator two products at a time (v_mfma_f32_32x32x2f32). mode "bf16":
+    the kernel values over s and the step s delta rounded to BF16, sixteen
+    products per accumulator step (v_mfma_f32_32x32x16_bf16). In both the
+    chunk sums add up in FP64, R is stored in FP32 after each update with the
+    block's rows set to 0, and block solves and W are FP64. The kernel columns
+    of each block are formed as needed, so large n fits."""
     from oracle import apo
-    K32 = apo.khat_block(p, slice(0, p.n), slice(0, p.n)).astype(np.float32)
     L = apo.factor(p)
     Wo, Ro = np.zeros_like(p.B), p.B.copy()
     W, R = np.zeros_like(p.B), p.B.astype(np.float32).astype(np.float64)
+    so = p.outputscale
     out = []
     for _ in range(epochs):
         apo.epoch(p, L, Wo, Ro)
@@ -63,12 +114,20 @@ def fp32_tile_floor(p, epochs: int) -> list[float]:
             s = p.block(j)
             d = apo.block_solve(apo.block_factor(L, p, j), R[s])
             W[s] += d
-            d32 = d.astype(np.float32)
-            upd = np.zeros_like(R)
-            for c0 in range(s.start, s.stop, 32):
-                cs = slice(c0, min(c0 + 32, s.stop))
-                upd += (K32[:, cs] @ d32[c0 - s.start:cs.stop - s.start]).astype(np.float64)
+            K = apo.khat_block(p, slice(0, p.n), s)
+            if mode == "bf16":
+                upd = so * _chunk_products(bf16(K / so), bf16(so * d), 16) / so
+            else:
+                upd = _chunk_products(K.astype(np.float32), d.astype(np.float32), 2)
+            del K
             R = (R - upd).astype(np.float32).astype(np.float64)
             R[s] = 0.0
-        out.append(float(np.linalg.norm(W - Wo) / np.linalg.norm(Wo)))
+        out.append((Wo.copy(), float(np.linalg.norm(W - Wo) / np.linalg.norm(Wo))))
+        if log:
+            log(f"[floor] {mode} epoch {len(out)}: {out[-1][1]:.3e}")
     return out
+
+
+def fp32_tile_floor(p, epochs: int) -> list[float]:
+    """Per-epoch FP32-tile rounding floor (tile_trajectory, mode "fp32")."""
+    return [f for _, f in tile_trajectory(p, epochs, "fp32")]

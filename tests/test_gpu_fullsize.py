@@ -3,8 +3,9 @@ times, on outputs the oracle computes one by one.
 
 Three block updates from Algorithm 1's start (block 0, a middle block and the
 ragged last block; or the greedy rule's choices) on the n = 2 000 000 workload
-with FP64 tiles and on the n = 4 000 000 workload with split tiles and greedy
-selection. For each update the GPU's residual before it (FP32, as stored) is
+with FP64 and FP32 tiles, on the n = 4 000 000 workload with split tiles and
+greedy selection, and on the n = 262 144 Matern-5/2 workload (d = 8, l = 16)
+with FP32, split and BF16 tiles. For each update the GPU's residual before it (FP32, as stored) is
 the common input, and the oracle gives, in FP64:
   - the greedy choice: argmax of the block norms (several blocks are a valid
     answer when their norms tie within the FP32 row-norm rounding);
@@ -14,8 +15,11 @@ the common input, and the oracle gives, in FP64:
     tail), compared element by element.
 Bounds: FP32 storage of R (2^-24 |R|), the step's relative difference (the
 GPU multiplies by the explicit FP64 inverse) times sum_q |K_iq||step_q|, and
-for split tiles the FP32 kernel values' rounding, u32 (4 + 4 |ln(k/s)|) per
-term (the argument of exp carries its own rounding times |ln(k/s)|)."""
+per term of that sum: FP32 tiles u32 (4 |R_i| + 6 |K_iq||step_q|) (kernel
+values within about 2 ulp, the step and each matrix-core sum rounded once);
+split tiles 8 u32 per term (three-term BF16 operands, and the matrix cores'
+16-product groups, which keep only the bits within FP32 range of the group's
+largest product); BF16 tiles 2^-7 per term (8-bit kernel values and step)."""
 from __future__ import annotations
 
 import numpy as np
@@ -55,11 +59,12 @@ def _check_update(p, w, R0, W0, R1, W1, blk, rows, tile):
     absk = np.abs(K)
     mag = absk @ np.abs(step)
     tol = U32 * np.abs(ref) + 2.0 * max(e_step, 1e-12) * mag
-    if tile != ap.TILE_FP64:
-        kn = absk.copy()
-        kn[rows[:, None] == np.arange(sl.start, sl.stop)[None, :]] -= p.noise
-        cond = np.abs(np.log(np.maximum(kn / p.outputscale, 1e-300)))
-        tol += U32 * (4.0 * np.abs(R0[rows]) + ((4.0 + 4.0 * cond) * absk) @ np.abs(step))
+    if tile == ap.TILE_FP32:
+        tol += U32 * (4.0 * np.abs(R0[rows]) + 6.0 * mag)
+    elif tile == ap.TILE_SPLIT:
+        tol += U32 * (4.0 * np.abs(R0[rows]) + 8.0 * mag)
+    elif tile == ap.TILE_BF16:
+        tol += U32 * 4.0 * np.abs(R0[rows]) + 2.0 ** -7 * mag
     err = np.abs(R1[rows].astype(np.float64) - ref)
     worst = float(np.max(err / np.maximum(tol, 1e-300)))
     amp = float(np.linalg.norm(mag) / max(np.linalg.norm(ref), 1e-300))
@@ -112,8 +117,21 @@ def test_fullsize_updates_fp64_tiles_n2m():
     _run(w, ap.TILE_FP64, blocks=[0, w.m // 2, w.m - 1])
 
 
+def test_fullsize_updates_fp32_tiles_n2m():
+    w = gen.c3()
+    _run(w, ap.TILE_FP32, blocks=[0, w.m // 2, w.m - 1])
+
+
 def test_fullsize_greedy_updates_split_tiles_n4m():
     _run(gen.c4(), ap.TILE_SPLIT)
+
+
+@pytest.mark.parametrize("tile", [ap.TILE_FP32, ap.TILE_SPLIT, ap.TILE_BF16])
+def test_fullsize_updates_c2(tile):
+    """The n = 262 144 workload (d = 8, Matern-5/2 ARD, l = 16, b = 1024): the
+    FP32 against BF16 tile comparison's configuration, three updates each."""
+    w = gen.c2()
+    _run(w, tile, blocks=[0, w.m // 2, w.m - 1])
 
 
 def test_fullsize_true_residual_sampled_rows():
