@@ -61,7 +61,7 @@ __device__ __forceinline__ float kmap_acc(double a) {
     const float e = __builtin_amdgcn_exp2f(-ah);
     return fmaf(e, al * -kInvLog2e, e);
   } else {
-    const float th = __builtin_amdgcn_sqrtf(ah);
+    const float th = __builtin_amdgcn_sqrtf(fmaxf(ah, 0.0f));
     const double thd = (double)th;
     const float ea = (float)fma(-thd, thd, a);  // a - t_hi^2, exact in FP64
     const float e = __builtin_amdgcn_exp2f(-th);
@@ -77,7 +77,22 @@ __device__ __forceinline__ float kmap_acc(double a) {
   }
 }
 
-// FP64 squared distance of a row's prepared features to a staged column's.
+// FP64 squared distance of a row's prepared features v_i (norm ni) to a staged
+// column's, through the norm expansion |v_i|^2 + |v_j|^2 - 2 v_i.v_j with the
+// column held as -2 v_j and its norm nj: d + 1 FP64 operations instead of 2d.
+// The features are centred and scaled, so |v|^2 stays within a few hundred
+// and the cancellation leaves an absolute error near 1e-13, far below the
+// FP32 map's rounding; the Matern maps clamp the result at 0.
+template <int DV>
+__device__ __forceinline__ double dist2n(const double* xr, double ni, const double* m2, double nj) {
+  double a = ni + nj;
+#pragma unroll
+  for (int k = 0; k < DV; ++k) a = fma(xr[k], m2[k], a);
+  return a;
+}
+
+// The same by exact differencing (2d FP64 operations; the split tiles use it:
+// there the expansion's extra registers cost more than its two operations).
 template <int DV>
 __device__ __forceinline__ double dist2(const double* xr, const double* xc) {
   double a = 0.0;
@@ -87,6 +102,28 @@ __device__ __forceinline__ double dist2(const double* xr, const double* xc) {
     a = fma(df, df, a);
   }
   return a;
+}
+
+template <int DV>
+__device__ __forceinline__ double norm2(const double* x) {
+  double a = 0.0;
+#pragma unroll
+  for (int k = 0; k < DV; ++k) a = fma(x[k], x[k], a);
+  return a;
+}
+
+// Stage a chunk's columns (rows cb .. cb + 31 of the prepared features) as
+// -2 v_j and their norms |v_j|^2. The caller brackets it with barriers.
+template <int DV, int DP>
+__device__ __forceinline__ void stage_cols(const double* __restrict__ xv, int64_t cb, double* sx,
+                                           double* sn) {
+  for (int e = threadIdx.x; e < kChunk * DP; e += blockDim.x) sx[e] = -2.0 * xv[cb * DP + e];
+  if (threadIdx.x < kChunk) {
+    double v[DV];
+#pragma unroll
+    for (int k = 0; k < DV; ++k) v[k] = xv[(cb + threadIdx.x) * DP + k];
+    sn[threadIdx.x] = norm2<DV>(v);
+  }
 }
 
 __device__ __forceinline__ bf16x8 load_bf16x8(const uint16_t* p) {
@@ -235,6 +272,7 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const double* __re
                                                     float* __restrict__ colsq, int want_rowsq,
                                                     int want_colsq) {
   __shared__ double sx[kChunk][DP];
+  __shared__ double sn[kChunk];
   __shared__ float sd[kChunk][kMaxL];
   const int blk = resolve_block(block, ctl);
   if (blk < 0) return;
@@ -245,11 +283,13 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const double* __re
   const int nl = lane % 32, g = lane / 32;
   const int64_t row0 = (int64_t)blockIdx.x * kRowsWG + wave * 64;
 
-  double xr[2][DV];
+  double xr[2][DV], nr[2];
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+  for (int t = 0; t < 2; ++t) {
 #pragma unroll
     for (int k = 0; k < DV; ++k) xr[t][k] = xv[(row0 + 32 * t + nl) * DP + k];
+    nr[t] = norm2<DV>(xr[t]);
+  }
   // Each chunk's 32 products accumulate in FP32 on the matrix cores; the chunk
   // sums then accumulate in FP64, so the rounding of the long sum over the
   // block stays at the level of one chunk.
@@ -262,7 +302,7 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const double* __re
   for (int ch = 0; ch < nch; ++ch) {
     const int64_t cb = start + (int64_t)ch * kChunk;
     __syncthreads();
-    for (int e = threadIdx.x; e < kChunk * DP; e += 256) (&sx[0][0])[e] = xv[cb * DP + e];
+    stage_cols<DV, DP>(xv, cb, &sx[0][0], sn);
     for (int e = threadIdx.x; e < kChunk * kMaxL; e += 256)
       (&sd[0][0])[e] = dtile[(int64_t)ch * kChunk * kMaxL + e];
     __syncthreads();
@@ -277,10 +317,11 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const double* __re
       double xc[DV];
 #pragma unroll
       for (int k = 0; k < DV; ++k) xc[k] = sx[cc][k];
+      const double nc = sn[cc];
       const float dv = sd[cc][nl];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        const float kv = kmap_acc<KERN>(dist2<DV>(xr[t], xc));
+        const float kv = kmap_acc<KERN>(dist2n<DV>(xr[t], nr[t], xc, nc));
         part[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(dv, kv, part[t], 0, 0, 0);
       }
     }
@@ -308,6 +349,7 @@ __global__ __launch_bounds__(256) void k_fused_fp32v(Layout L, const double* __r
                                                      float* __restrict__ colsq, int want_rowsq,
                                                      int want_colsq) {
   __shared__ double sx[kChunk][DP];
+  __shared__ double sn[kChunk];
   __shared__ float sd[kChunk][NV];
   __shared__ float red[4][NV];
   const int blk = resolve_block(block, ctl);
@@ -322,6 +364,7 @@ __global__ __launch_bounds__(256) void k_fused_fp32v(Layout L, const double* __r
   double xr[DV];
 #pragma unroll
   for (int k = 0; k < DV; ++k) xr[k] = xv[row * DP + k];
+  const double nr = norm2<DV>(xr);
   double acc[NV];
 #pragma unroll
   for (int c = 0; c < NV; ++c) acc[c] = 0.0;
@@ -329,7 +372,7 @@ __global__ __launch_bounds__(256) void k_fused_fp32v(Layout L, const double* __r
   for (int ch = 0; ch < nch; ++ch) {
     const int64_t cb = start + (int64_t)ch * kChunk;
     __syncthreads();
-    for (int e = threadIdx.x; e < kChunk * DP; e += 256) (&sx[0][0])[e] = xv[cb * DP + e];
+    stage_cols<DV, DP>(xv, cb, &sx[0][0], sn);
     for (int e = threadIdx.x; e < kChunk * NV; e += 256)
       sd[e / NV][e % NV] = dtile[((int64_t)ch * kChunk + e / NV) * kMaxL + e % NV];
     __syncthreads();
@@ -338,7 +381,7 @@ __global__ __launch_bounds__(256) void k_fused_fp32v(Layout L, const double* __r
     for (int c = 0; c < NV; ++c) part[c] = 0.f;
 #pragma unroll 4
     for (int j = 0; j < kChunk; ++j) {
-      const float kv = kmap_acc<KERN>(dist2<DV>(xr, sx[j]));
+      const float kv = kmap_acc<KERN>(dist2n<DV>(xr, nr, sx[j], sn[j]));
 #pragma unroll
       for (int c = 0; c < NV; ++c) part[c] = fmaf(kv, sd[j][c], part[c]);
     }
@@ -383,7 +426,7 @@ __global__ __launch_bounds__(256) void k_fused_fp32v(Layout L, const double* __r
 }
 
 // Split path: FP32 kernel tiles (FP64 squared distance of the FP64 prepared
-// features, kmap_acc) and the product on BF16 matrix cores. The tile K = kh + km + kl and the
+// features by differencing, kmap_acc) and the product on BF16 matrix cores. The tile K = kh + km + kl and the
 // step d = dh + dm + dl are each held as three BF16 terms (24 significant bits),
 // and the six partial products with term orders summing to at most 2,
 //   dl kh + dh kl + dm km + dm kh + dh km + dh kh   (small to large),

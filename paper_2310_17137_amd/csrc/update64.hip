@@ -4,7 +4,7 @@
 // cancels to |R| from terms as large as |K||delta| (far larger when K^_{I,I} is
 // close to singular), so the rounding of the kernel values, not of R, decides
 // whether the maintained residual stays true. Here every kernel value is FP64
-// (exact differencing of the inputs over the lengthscales, FP64 map) and the
+// (squared distance of the centred inputs over the lengthscales, FP64 map) and the
 // product runs on v_mfma_f64_16x16x4f64 with FP64 accumulation; only the stored
 // residual is FP32, whose rounding is relative to |R| itself.
 //
@@ -14,6 +14,14 @@
 // step of 4 columns a lane evaluates one kernel value per row tile (row
 // lane % 16, column lane / 16) and the matrix cores accumulate
 // acc[c][i] += delta^T[c][j] K^T[j][i] for 16 right-hand sides per half.
+//
+// The squared distance comes from the norm expansion of the centred features
+// u = (x - mu) / ell: |u_i|^2 + |u_j|^2 - 2 u_i.u_j, with the column held as
+// -2 u_j and its norm, d + 1 FP64 operations where differencing takes 2d. The
+// cancellation costs an absolute error near 1e-13 in r^2 (|u|^2 is at most a
+// few hundred), far below the FP32 rounding of the stored residual; the FP64
+// references (true residual, posterior mean, MLL gradient) keep exact
+// differencing.
 #include <algorithm>
 
 #include "ap_internal.h"
@@ -25,6 +33,51 @@ namespace {
 typedef __attribute__((ext_vector_type(4))) double f64x4;
 constexpr int kCols64 = 64;
 
+// Row features centred and scaled, u = (x - mu) / ell (zero past d and n),
+// and |u|^2 in the order the staged columns use.
+template <int DV>
+__device__ __forceinline__ void row_feat(const float* __restrict__ X, int64_t i, int64_t n,
+                                         int d, const Params& P, const Ctl* ctl, double* u,
+                                         double* nu) {
+  double a = 0.0;
+#pragma unroll
+  for (int k = 0; k < DV; ++k) {
+    u[k] = (i < n && k < d) ? ((double)X[i * d + k] - ctl->mu[k]) / P.ell[k] : 0.0;
+    a = fma(u[k], u[k], a);
+  }
+  *nu = a;
+}
+
+// A block's columns c0 .. c0 + kCols64 - 1 staged as -2 u_j (sx) and |u_j|^2
+// (sn), one column per thread of the first kCols64; columns past len are zero.
+// The caller brackets it with barriers.
+template <int DV, int DP>
+__device__ __forceinline__ void stage_cols64(const float* __restrict__ X, int64_t start, int c0,
+                                             int len, int d, const Params& P, const Ctl* ctl,
+                                             double (*sx)[DP], double* sn) {
+  if (threadIdx.x < kCols64) {
+    const int jj = threadIdx.x;
+    const bool in = c0 + jj < len;
+    double a = 0.0;
+#pragma unroll
+    for (int k = 0; k < DP; ++k) {
+      double u = 0.0;
+      if (in && k < d) u = ((double)X[(start + c0 + jj) * d + k] - ctl->mu[k]) / P.ell[k];
+      a = fma(u, u, a);
+      sx[jj][k] = -2.0 * u;
+    }
+    sn[jj] = a;
+  }
+}
+
+template <int DV>
+__device__ __forceinline__ double dist2n64(const double* u, double nu, const double* m2, double nj) {
+  double a = nu + nj;
+#pragma unroll
+  for (int k = 0; k < DV; ++k) a = fma(u[k], m2[k], a);
+  return a;
+}
+
 template <int KERN, int DV, int DP, int NH>
 __global__ __launch_bounds__(256) void k_fused_fp64(Layout L, Params P, const float* __restrict__ X,
                                                     const double* __restrict__ delta,
@@ -34,6 +87,7 @@ __global__ __launch_bounds__(256) void k_fused_fp64(Layout L, Params P, const fl
                                                     float* __restrict__ colsq, int want_rowsq,
                                                     int want_colsq) {
   __shared__ double sx[kCols64][DP];
+  __shared__ double sn[kCols64];
   __shared__ double sd[kCols64][16 * NH];
   __shared__ float red[4][kMaxL];
   __shared__ double etab[kExpTab];  // s * 2^(j/256) for the exponential
@@ -47,17 +101,9 @@ __global__ __launch_bounds__(256) void k_fused_fp64(Layout L, Params P, const fl
   const int ln = lane % 16, lg = lane / 16;
   const int64_t row0 = (int64_t)blockIdx.x * kRowsWG + wave * 64;
 
-  double inv_ell[DV];
+  double xi[4][DV], ni[4];
 #pragma unroll
-  for (int k = 0; k < DV; ++k) inv_ell[k] = k < d ? 1.0 / P.ell[k] : 0.0;
-  double xi[4][DV];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int64_t i = row0 + 16 * t + ln;
-#pragma unroll
-    for (int k = 0; k < DV; ++k)
-      xi[t][k] = (i < L.n && k < d) ? (double)X[i * d + k] * inv_ell[k] : 0.0;
-  }
+  for (int t = 0; t < 4; ++t) row_feat<DV>(X, row0 + 16 * t + ln, L.n, d, P, ctl, xi[t], &ni[t]);
   f64x4 acc[4][NH];
 #pragma unroll
   for (int t = 0; t < 4; ++t)
@@ -66,10 +112,7 @@ __global__ __launch_bounds__(256) void k_fused_fp64(Layout L, Params P, const fl
 
   for (int c0 = 0; c0 < len; c0 += kCols64) {
     __syncthreads();
-    for (int e = threadIdx.x; e < kCols64 * DP; e += 256) {
-      const int jj = e / DP, k = e % DP;
-      sx[jj][k] = (c0 + jj < len && k < d) ? (double)X[(start + c0 + jj) * d + k] / P.ell[k] : 0.0;
-    }
+    stage_cols64<DV, DP>(X, start, c0, len, d, P, ctl, sx, sn);
     for (int e = threadIdx.x; e < kCols64 * 16 * NH; e += 256) {
       const int jj = e / (16 * NH), c = e % (16 * NH);
       sd[jj][c] = (c0 + jj < len) ? delta[(size_t)(c0 + jj) * kMaxL + c] : 0.0;
@@ -81,14 +124,14 @@ __global__ __launch_bounds__(256) void k_fused_fp64(Layout L, Params P, const fl
       double a[NH];
 #pragma unroll
       for (int h = 0; h < NH; ++h) a[h] = sd[jj][16 * h + ln];
+      double xc[DV];
+#pragma unroll
+      for (int k = 0; k < DV; ++k) xc[k] = sx[jj][k];
+      const double nc = sn[jj];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        double r2 = 0.0;
-#pragma unroll
-        for (int k = 0; k < DV; ++k) {
-          const double df = xi[t][k] - sx[jj][k];
-          r2 = fma(df, df, r2);
-        }
+        double r2 = dist2n64<DV>(xi[t], ni[t], xc, nc);
+        if constexpr (KERN != 0) r2 = fmax(r2, 0.0);
         const double kv = kernel_fp64<KERN>(r2, etab);
 #pragma unroll
         for (int h = 0; h < NH; ++h)
@@ -167,6 +210,7 @@ __global__ __launch_bounds__(256) void k_fused_fp64v(Layout L, Params P,
                                                      int want_colsq) {
   constexpr int NQ = (NV + 3) / 4;  // output columns per lane
   __shared__ double sx[kCols64][DP];
+  __shared__ double sn[kCols64];
   __shared__ double sd[kCols64][NV];
   __shared__ float red[4][kMaxL];
   __shared__ double etab[kExpTab];  // s * 2^(j/256) for the exponential
@@ -180,17 +224,9 @@ __global__ __launch_bounds__(256) void k_fused_fp64v(Layout L, Params P,
   const int ln = lane % 16, lg = lane / 16;
   const int64_t row0 = (int64_t)blockIdx.x * kRowsWG + wave * 64;
 
-  double inv_ell[DV];
+  double xi[4][DV], ni[4];
 #pragma unroll
-  for (int k = 0; k < DV; ++k) inv_ell[k] = k < d ? 1.0 / P.ell[k] : 0.0;
-  double xi[4][DV];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int64_t i = row0 + 16 * t + ln;
-#pragma unroll
-    for (int k = 0; k < DV; ++k)
-      xi[t][k] = (i < L.n && k < d) ? (double)X[i * d + k] * inv_ell[k] : 0.0;
-  }
+  for (int t = 0; t < 4; ++t) row_feat<DV>(X, row0 + 16 * t + ln, L.n, d, P, ctl, xi[t], &ni[t]);
   double acc[4][NV];
 #pragma unroll
   for (int t = 0; t < 4; ++t)
@@ -199,10 +235,7 @@ __global__ __launch_bounds__(256) void k_fused_fp64v(Layout L, Params P,
 
   for (int c0 = 0; c0 < len; c0 += kCols64) {
     __syncthreads();
-    for (int e = threadIdx.x; e < kCols64 * DP; e += 256) {
-      const int jj = e / DP, k = e % DP;
-      sx[jj][k] = (c0 + jj < len && k < d) ? (double)X[(start + c0 + jj) * d + k] / P.ell[k] : 0.0;
-    }
+    stage_cols64<DV, DP>(X, start, c0, len, d, P, ctl, sx, sn);
     for (int e = threadIdx.x; e < kCols64 * NV; e += 256) {
       const int jj = e / NV, c = e % NV;
       sd[jj][c] = (c0 + jj < len) ? delta[(size_t)(c0 + jj) * kMaxL + c] : 0.0;
@@ -214,14 +247,14 @@ __global__ __launch_bounds__(256) void k_fused_fp64v(Layout L, Params P,
       double a[NV];
 #pragma unroll
       for (int c = 0; c < NV; ++c) a[c] = sd[jj][c];
+      double xc[DV];
+#pragma unroll
+      for (int k = 0; k < DV; ++k) xc[k] = sx[jj][k];
+      const double nc = sn[jj];
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        double r2 = 0.0;
-#pragma unroll
-        for (int k = 0; k < DV; ++k) {
-          const double df = xi[t][k] - sx[jj][k];
-          r2 = fma(df, df, r2);
-        }
+        double r2 = dist2n64<DV>(xi[t], ni[t], xc, nc);
+        if constexpr (KERN != 0) r2 = fmax(r2, 0.0);
         const double kv = kernel_fp64<KERN>(r2, etab);
 #pragma unroll
         for (int c = 0; c < NV; ++c) acc[t][c] = fma(kv, a[c], acc[t][c]);
