@@ -147,11 +147,14 @@ def oracle_problem(w):
                        b=w.b, order=0)
 
 
-def oracle_rho_sample(p, W, rows: int, seed: int = 0) -> dict:
+def oracle_rho_sample(p, W, rows: int, seed: int = 0, R_gpu=None) -> dict:
     """The FP64 oracle's estimate of mean_c ||r_c|| / ||b_c|| for R = B - K^ W
     from `rows` rows drawn uniformly without replacement: ||r_c||^2 is n / k
     times the sum over the sampled rows; the standard error is the delta
-    method's over the rows' contributions."""
+    method's over the rows' contributions. With R_gpu (the GPU's residual,
+    n x l) also the relative difference of its sampled rows from the oracle's
+    (after an FP64 true residual: that residual's FP32 storage; for a
+    maintained residual: its drift)."""
     from oracle import apo
     rng = np.random.default_rng(seed)
     idx = np.sort(rng.choice(p.n, size=min(rows, p.n), replace=False))
@@ -167,7 +170,10 @@ def oracle_rho_sample(p, W, rows: int, seed: int = 0) -> dict:
     g = np.where(ok & (S > 0), 1.0 / (2.0 * p.l * np.where(ok, bn, 1.0) * np.sqrt(np.maximum(S, 1e-300))), 0.0)
     z = p.n * (sq @ g)
     se = float(np.std(z, ddof=1) / math.sqrt(k)) if k > 1 else float("nan")
-    return {"rho": rho, "se": se, "rows": int(k), "seconds": dt, "threads": apo.num_threads()}
+    out = {"rho": rho, "se": se, "rows": int(k), "seconds": dt, "threads": apo.num_threads()}
+    if R_gpu is not None:
+        out["rows_rel_diff"] = float(np.linalg.norm(R_gpu[idx] - r) / max(np.linalg.norm(r), 1e-300))
+    return out
 
 
 class OracleChecks:
@@ -179,8 +185,8 @@ class OracleChecks:
         self.ex = cf.ThreadPoolExecutor(max_workers=1)
         self.jobs = {}
 
-    def submit(self, key, p, W_host, rows, seed=0):
-        self.jobs[key] = self.ex.submit(oracle_rho_sample, p, W_host, rows, seed)
+    def submit(self, key, p, W_host, rows, seed=0, R_host=None):
+        self.jobs[key] = self.ex.submit(oracle_rho_sample, p, W_host, rows, seed, R_host)
 
     def get(self, key):
         f = self.jobs.get(key)
@@ -267,7 +273,7 @@ def default_time_to_tol(checks, runs=TTT_RUNS, max_epochs=60, oracle_rows=2048):
         rec["refine_every"] = refine
         out["runs"][name] = rec
         if "W" in r:
-            checks.submit(("ttt", name), p, r.pop("W"), oracle_rows, seed=11)
+            checks.submit(("ttt", name), p, r.pop("W"), oracle_rows, seed=11, R_host=r.pop("R"))
     del X, B
     torch.cuda.empty_cache()
     return out, p
@@ -315,7 +321,8 @@ def time_to_tol(w, make, B, runs):
                         "final_tile": TILE_NAMES[st.tile], "escalated_at": st.escalated_at,
                         "restarted_at": st.restarted_at})
             run["W"] = W.cpu().numpy()
-        log(f"[tol] {name}: " + json.dumps({k: v for k, v in run.items() if k != "W"}))
+            run["R"] = R.cpu().numpy().astype(np.float64)
+        log(f"[tol] {name}: " + json.dumps({k: v for k, v in run.items() if k not in ("W", "R")}))
         out.append(run)
         del s, W, R
         import torch
@@ -609,6 +616,7 @@ def main():
             r = time_to_tol(w, lambda t, re=refine: make_solver(w, X, t, re), B,
                             [(name, tile)])[0]
             r.pop("W", None)
+            r.pop("R", None)
             runs.append(r)
         print(json.dumps({"time_to_tol": runs, "workload": describe(w), "tol": w.tol,
                           "refine_every": w.refine_every, "max_epochs": w.max_epochs}),
@@ -685,7 +693,8 @@ def main():
             log(f"[bench] {res['tile']}: FP64 true ratio {res['rho_true']:.6f} "
                 f"(maintained {rho:.6f}) in {res['true_residual_s']:.2f} s")
         if p_main is not None and args.oracle_rows > 0:
-            checks.submit("main", p_main, W.cpu().numpy(), args.oracle_rows, seed=5)
+            checks.submit("main", p_main, W.cpu().numpy(), args.oracle_rows, seed=5,
+                          R_host=R.cpu().numpy().astype(np.float64))
         # per-phase split and the fused kernel's launch duration: one more
         # epoch with eager launches and events (outside the timed region)
         s.profile(True)

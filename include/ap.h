@@ -161,7 +161,10 @@ ap_status ap_factor_blocks(const ap_config* cfg, const float* X, void* ws, size_
 ap_status ap_reset(ap_handle h, const ap_state* st, hipStream_t stream);
 
 /* Run `epochs` epochs of m block updates on each of `count` problems (h[i],
- * st[i]); each problem's arithmetic is the same whatever count is. After each
+ * st[i]); each problem's arithmetic is the same whatever count is. The
+ * problems' epochs are enqueued one after another on the stream, each as that
+ * handle's captured epoch graph (one replay per epoch); ap_batch_step is the
+ * entry point that groups many problems into one launch per phase. After each
  * epoch the maintained-residual ratio is stored on the device (read it with
  * ap_rel_residual). Asynchronous. */
 ap_status ap_epoch(const ap_handle* h, const ap_state* st, int32_t count, int32_t epochs,
