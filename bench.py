@@ -90,7 +90,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def workload(name: str):
+def workload(name: str, n: int = 0):
     from paper_2310_17137_amd import gen
     if name == "c3" or name.startswith("c3-"):
         # variants of the same inputs: c3-noise<sigma^2>, c3-l<right-hand sides>, or both
@@ -103,6 +103,8 @@ def workload(name: str):
             kw["noise"] = float(m.group(1))
         if m.group(2):
             kw["l"] = int(m.group(2))
+        if n > 0:
+            kw["n"] = n
         return gen.c3(**kw)
     if name == "c2":
         return gen.c2()
@@ -530,6 +532,10 @@ def main():
                           "FP64 true-residual refinement and confirmation) and print the time "
                           "to the tolerance instead of the epoch-rate line")
     ap_.add_argument("--b", type=int, default=0, help="override the workload's block size")
+    ap_.add_argument("--n", type=int, default=0,
+                     help="points of the n = 2M recipe's generator (0: 2 000 000)")
+    ap_.add_argument("--lookahead", type=int, default=1,
+                     help="cyclic look-ahead group (ap_set_lookahead) of the timed path")
     ap_.add_argument("--order", default="", choices=["", "cyclic", "greedy", "random"],
                      help="override the workload's block selection")
     ap_.add_argument("--max-epochs", type=int, default=0,
@@ -573,7 +579,7 @@ def main():
         return
     ap.load()
     t = time.perf_counter()
-    w = workload(args.workload)
+    w = workload(args.workload, args.n)
     if args.b > 0:
         w.b = args.b
     if args.order:
@@ -645,10 +651,12 @@ def main():
         region; then one profiled epoch (eager launches with per-phase events)
         for the roofline, outside it."""
         s, t_factor = make(tile)
+        if args.lookahead > 1:
+            s.set_lookahead(args.lookahead)
         W, R = s.new_state(B)
         s.reset(B, W, R)
         res = {"tile": TILE_NAMES[tile], "factor_s": t_factor, "steps": steps,
-               "warmup": warmup, "refine_every": refine_every,
+               "warmup": warmup, "refine_every": refine_every, "lookahead": args.lookahead,
                "workspace_gb": s.ws_bytes / 1e9}
         epoch = 0
 
