@@ -268,6 +268,7 @@ def default_time_to_tol(checks, runs=TTT_RUNS, max_epochs=60, oracle_rows=2048):
            "order, b = 4096, on the n = 2M inputs", "tol": w.tol, "max_epochs": w.max_epochs,
            "runs": {}}
     for name, tile, refine in runs:
+        log(f"[stage] time to tolerance: {name}")
         r = time_to_tol(w, lambda t, re=refine: make_solver(w, X, t, re), B, [(name, tile)])[0]
         rec = {k: r.get(k) for k in ("converged", "epochs", "time_to_tol_s", "factor_s",
                                      "t_epochs", "t_refine", "rho_maintained", "rho_true",
@@ -757,10 +758,12 @@ def main():
         return res
 
     main_tile = tiles[args.main]
+    log(f"[stage] main path: {args.main} tiles")
     main = run_main(main_tile, args.steps, args.warmup)
     paths = {}
     for name in ("fp64", "split", "bf16", "fp32"):
         if name != args.main and args.other_steps > 0 and name not in args.skip.split(","):
+            log(f"[stage] other path: {name} tiles")
             paths[name] = run_compare(w, B, make, tiles[name], args.other_steps, 1)
 
     # the same inputs at sigma^2 = 1e-2, where every FP32-grade path holds
@@ -771,6 +774,7 @@ def main():
         B2 = torch.from_numpy(w2.B).to(dev)
         noise2 = {"workload": describe(w2), "paths": {}}
         for name in ("split", "fp32"):
+            log(f"[stage] sigma^2 = 1e-2: {name} tiles")
             noise2["paths"][name] = run_compare(w2, B2, lambda t: make_solver(w2, X, t),
                                                 tiles[name], 2, 1)
         del B2
@@ -807,6 +811,7 @@ def main():
 
     serving = None
     if not args.no_serve:
+        log("[stage] serving stream")
         serving = serving_run(checks)
 
     main["oracle_sampled"] = checks.get("main")
@@ -820,6 +825,7 @@ def main():
 
     cpu = None
     if not args.no_cpu and args.cpu_updates > 0:
+        log("[stage] oracle on the host")
         cpu = cpu_baseline(w, args.cpu_updates)
         log(f"[bench] oracle on {cpu['cores']} host threads: {cpu['value']:.3e} epochs/s")
 

@@ -69,12 +69,16 @@ __host__ __device__ inline int32_t random_block(unsigned long long seed, unsigne
 }
 
 // Block of this launch, or -1 when a batch step skips a held problem (uniform
-// over the workgroup).
-__device__ __forceinline__ int resolve_block(int block, const struct Ctl* ctl) {
-  if (block >= 0) return block;
-  if (block == kBlockSel) return ctl->sel;
-  if (!ctl->run) return -1;
-  return block == kBlockBatchCyclic ? ctl->cursor : ctl->sel;
+// over the workgroup). An index read from the control block outside [0, m)
+// (which the selection kernels never write) also gives -1, so a launch never
+// addresses a block that does not exist.
+__device__ __forceinline__ int resolve_block(int block, const struct Ctl* ctl, int m) {
+  int b = block;
+  if (block < 0) {
+    if (block != kBlockSel && !ctl->run) return -1;
+    b = block == kBlockBatchCyclic ? ctl->cursor : ctl->sel;
+  }
+  return b >= 0 && b < m ? b : -1;
 }
 
 // Kernel map constants. The prepared features v = (x - mu) / ell * c_feat make

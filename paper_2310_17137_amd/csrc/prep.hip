@@ -300,12 +300,16 @@ __global__ __launch_bounds__(256) void k_block_norms(Layout L, const float* __re
 }
 
 // Modified Gauss-Southwell rule: argmax over blocks, ties to the lowest index.
+// A NaN norm is never selected. If no block has a norm that compares (every
+// one NaN), block 0 is taken and the status word marks the residual as not
+// finite, so the selection is always a valid block and the host sees the
+// failure at the epoch-end check.
 __device__ __forceinline__ void argmax_body(const Layout& L, const double* __restrict__ nrm,
                                             Ctl* ctl) {
   __shared__ double bv[256];
   __shared__ int bi[256];
   double best = -1.0;
-  int idx = 0x7fffffff;
+  int idx = -1;
   for (int j = threadIdx.x; j < L.m; j += 256) {
     double v = nrm[j];
     if (v > best) {
@@ -327,7 +331,14 @@ __device__ __forceinline__ void argmax_body(const Layout& L, const double* __res
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) ctl->sel = bi[0];
+  if (threadIdx.x == 0) {
+    if (bi[0] >= 0 && bi[0] < L.m) {
+      ctl->sel = bi[0];
+    } else {
+      ctl->sel = 0;
+      ctl->status = -3;
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void k_argmax(Layout L, const double* __restrict__ nrm,

@@ -79,7 +79,7 @@ __global__ __launch_bounds__(256) void k_bs_partial(Layout L, const double* __re
                                                     const float* __restrict__ R,
                                                     double* __restrict__ part) {
   __shared__ double smem[bs_smem<LB>()];
-  const int blk = resolve_block(block, ctl);
+  const int blk = resolve_block(block, ctl, L.m);
   if (blk < 0) return;
   bs_partial_body<LB>(L, kinv, blk, R, part, (int)blockIdx.x, smem);
 }
@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void k_bs_finish(Layout L, const Ctl* __restri
                                                    double* __restrict__ W,
                                                    double* __restrict__ delta, void* dtile,
                                                    int coff) {
-  const int blk = resolve_block(block, ctl);
+  const int blk = resolve_block(block, ctl, L.m);
   if (blk < 0) return;
   bs_finish_body(L, blk, L.tile, s, part, W, delta, dtile, (int)blockIdx.x * 256 + threadIdx.x,
                  coff);
@@ -156,7 +156,7 @@ __global__ __launch_bounds__(256) void g_bs_partial(Group g) {
   const int p = group_job(g, &wg);
   const Desc* ds = g.desc[p];
   const Layout L = ds->L;
-  const int blk = resolve_block(batch_code(L), ds->D.ctl);
+  const int blk = resolve_block(batch_code(L), ds->D.ctl, L.m);
   if (blk < 0) return;
   const double* kinv = ds->D.kinv;
   double* part = ds->D.bspart;
@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256) void g_bs_finish(Group g) {
   const int p = group_job(g, &wg);
   const Desc* ds = g.desc[p];
   const Layout L = ds->L;
-  const int blk = resolve_block(batch_code(L), ds->D.ctl);
+  const int blk = resolve_block(batch_code(L), ds->D.ctl, L.m);
   if (blk < 0) return;
   bs_finish_body(L, blk, g.tile[p], ds->P.s, ds->D.bspart, g.W[p], ds->D.delta, ds->D.dtile,
                  wg * 256 + threadIdx.x, 0);

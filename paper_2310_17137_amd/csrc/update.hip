@@ -213,7 +213,7 @@ __global__ __launch_bounds__(256) void k_fused_bf16(Layout L, const uint16_t* __
                                                     float* __restrict__ rowsq,
                                                     float* __restrict__ colsq, int want_rowsq,
                                                     int want_colsq) {
-  const int blk = resolve_block(block, ctl);
+  const int blk = resolve_block(block, ctl, L.m);
   if (blk < 0) return;
   const Span S = block_span(L, blk, sp);
   const int64_t start = S.cstart;
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const double* __re
   __shared__ double sx[kChunk][DP];
   __shared__ double sn[kChunk];
   __shared__ float sd[kChunk][kMaxL];
-  const int blk = resolve_block(block, ctl);
+  const int blk = resolve_block(block, ctl, L.m);
   if (blk < 0) return;
   const Span S = block_span(L, blk, sp);
   const int64_t start = S.cstart;
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(256) void k_fused_fp32v(Layout L, const double* __r
   __shared__ double sn[kChunk];
   __shared__ float sd[kChunk][NV];
   __shared__ float red[4][NV];
-  const int blk = resolve_block(block, ctl);
+  const int blk = resolve_block(block, ctl, L.m);
   if (blk < 0) return;
   const Span S = block_span(L, blk, sp);
   const int64_t start = S.cstart;
@@ -518,7 +518,7 @@ __global__ __launch_bounds__(256) void k_fused_split(Layout L, const double* __r
                                                      float* __restrict__ colsq, int want_rowsq,
                                                      int want_colsq) {
   __shared__ double sx[kChunk * DP];
-  const int blk = resolve_block(block, ctl);
+  const int blk = resolve_block(block, ctl, L.m);
   if (blk < 0) return;
   split_body<KERN, DV, DP>(L, xv, dtile, block_span(L, blk, sp), R, rowsq, colsq, want_rowsq,
                            want_colsq, (int)blockIdx.x, sx);
@@ -561,7 +561,7 @@ __global__ __launch_bounds__(256) void g_fused_split(Group g) {
   const Desc* ds = g.desc[p];
   const Layout L = ds->L;
   const int blk =
-      resolve_block(L.order != 0 ? kBlockBatchSel : kBlockBatchCyclic, ds->D.ctl);
+      resolve_block(L.order != 0 ? kBlockBatchSel : kBlockBatchCyclic, ds->D.ctl, L.m);
   if (blk < 0) return;
   if (L.kernel == 0)
     split_dispatch<0, WIDE>(L, ds, blk, g.R[p], wg, sx);

@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void k_fused_fp64(Layout L, Params P, const fl
   __shared__ double sd[kCols64][16 * NH];
   __shared__ float red[4][kMaxL];
   __shared__ double etab[kExpTab];  // s * 2^(j/256) for the exponential
-  const int blk = resolve_block(block, ctl);
+  const int blk = resolve_block(block, ctl, L.m);
   if (blk < 0) return;
   scaled_exp_table(etab, P.s);  // visible after the first barrier of the chunk loop
   const Span S = block_span(L, blk, sp);
@@ -216,7 +216,7 @@ __global__ __launch_bounds__(256) void k_fused_fp64v(Layout L, Params P,
   __shared__ double sd[kCols64][NV];
   __shared__ float red[4][kMaxL];
   __shared__ double etab[kExpTab];  // s * 2^(j/256) for the exponential
-  const int blk = resolve_block(block, ctl);
+  const int blk = resolve_block(block, ctl, L.m);
   if (blk < 0) return;
   scaled_exp_table(etab, P.s);  // visible after the first barrier of the chunk loop
   const Span S = block_span(L, blk, sp);

@@ -463,6 +463,42 @@ def test_nonfinite_rhs_is_reported():
     assert e.value.code == ap.ERR_NONFINITE
 
 
+@pytest.mark.parametrize("tile", [ap.TILE_FP32, ap.TILE_FP64])
+@pytest.mark.parametrize("where", ["one_block", "every_block"])
+def test_greedy_never_selects_past_the_blocks(tile, where):
+    """Modified Gauss-Southwell rule on a residual with NaN rows: a block whose
+    norm is NaN is never selected; when every norm is NaN the rule takes block
+    0 and sets the status word. Either way every update stays on the m blocks
+    and the epoch ends with AP_ERR_NONFINITE."""
+    print(f"[case] greedy nonfinite tile={tile} where={where}", flush=True)
+    n, b = 400, 50  # m = 8
+    X = torch.rand(n, 3, device="cuda")
+    s = ap.Solver(X, l=2, b=b, kernel=ap.RBF, lengthscale=0.5, noise=0.1, order=ap.GREEDY,
+                  tile=tile)
+    B = torch.rand(n, 2, device="cuda")
+    if where == "one_block":
+        B[17, 1] = float("nan")  # block 0
+    else:
+        B[::b, 0] = float("nan")  # first row of every block
+    W, R = s.new_state(B)
+    s.reset(B, W, R)
+    s.epoch(B, W, R, 2)
+    torch.cuda.synchronize()
+    assert s.peek().status == ap.ERR_NONFINITE
+    with pytest.raises(ap.ApError) as e:
+        s.rel_residual()
+    assert e.value.code == ap.ERR_NONFINITE
+    Wh = W.cpu().numpy()
+    if where == "one_block":
+        # block 0 never updated; every other block's steps finite
+        assert np.all(Wh[:b] == 0.0)
+        assert np.all(np.isfinite(Wh[b:]))
+        assert np.any(Wh[b:] != 0.0)
+    else:
+        # only block 0 ever updated
+        assert np.all(Wh[b:] == 0.0)
+
+
 @pytest.mark.parametrize("kern", [apo.RBF, apo.MATERN32, apo.MATERN52])
 @pytest.mark.parametrize("tile", [ap.TILE_FP32, ap.TILE_SPLIT, ap.TILE_BF16, ap.TILE_FP64])
 def test_kernel_column_through_unit_blocks(kern, tile):
