@@ -20,8 +20,10 @@ ratio of the final W, the other tile paths on the same problem (FP64, split,
 BF16 tiles) and on the same inputs at sigma^2 = 1e-2, the time to a relative
 residual of 1e-2 (factor included) for the FP64, mixed, plain FP32 and split
 paths on the paper's test-time solve (the target column alone, greedy order,
-b = 4096), a short serving run on a scaled stream of the serving recipe, and
-the FP64 CPU oracle timed on a bounded sample on this host.
+b = 4096) and a short serving run on a scaled stream of the serving recipe (both
+optional, below), and
+the FP64 CPU oracle timed on a bounded sample on this host. The
+time-to-tolerance runs and the serving run are added with --ttt and --serve.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -516,16 +518,18 @@ def main():
                           "(-1: the workload's, 5 for the n = 2M recipe; 0: none)")
     ap_.add_argument("--other-steps", type=int, default=1,
                      help="timed epochs of each other tile path (0: main path only)")
-    ap_.add_argument("--skip", default="", help="comma-separated tile paths not to run")
+    ap_.add_argument("--skip", default="bf16",
+                     help="comma-separated tile paths not to run (default: bf16, which does "
+                          "not hold the true residual on this system)")
     ap_.add_argument("--cpu-updates", type=int, default=5)
     ap_.add_argument("--oracle-rows", type=int, default=1024,
                      help="rows of the oracle's sampled FP64 residual of the timed path's W")
     ap_.add_argument("--no-cpu", action="store_true")
     ap_.add_argument("--no-true-residual", action="store_true")
-    ap_.add_argument("--no-ttt", action="store_true",
-                     help="skip the time-to-tolerance runs of the default line")
-    ap_.add_argument("--no-serve", action="store_true",
-                     help="skip the serving run of the default line")
+    ap_.add_argument("--ttt", action="store_true",
+                     help="add the time-to-tolerance runs (greedy test-time solve) to the line")
+    ap_.add_argument("--serve", action="store_true",
+                     help="add the serving run (batch steps) to the line")
     ap_.add_argument("--no-noise2", action="store_true",
                      help="skip the sigma^2 = 1e-2 comparison of the default line")
     ap_.add_argument("--time-to-tol", default="",
@@ -535,8 +539,6 @@ def main():
     ap_.add_argument("--b", type=int, default=0, help="override the workload's block size")
     ap_.add_argument("--n", type=int, default=0,
                      help="points of the n = 2M recipe's generator (0: 2 000 000)")
-    ap_.add_argument("--lookahead", type=int, default=1,
-                     help="cyclic look-ahead group (ap_set_lookahead) of the timed path")
     ap_.add_argument("--order", default="", choices=["", "cyclic", "greedy", "random"],
                      help="override the workload's block selection")
     ap_.add_argument("--max-epochs", type=int, default=0,
@@ -652,12 +654,10 @@ def main():
         region; then one profiled epoch (eager launches with per-phase events)
         for the roofline, outside it."""
         s, t_factor = make(tile)
-        if args.lookahead > 1:
-            s.set_lookahead(args.lookahead)
         W, R = s.new_state(B)
         s.reset(B, W, R)
         res = {"tile": TILE_NAMES[tile], "factor_s": t_factor, "steps": steps,
-               "warmup": warmup, "refine_every": refine_every, "lookahead": args.lookahead,
+               "warmup": warmup, "refine_every": refine_every,
                "workspace_gb": s.ws_bytes / 1e9}
         epoch = 0
 
@@ -804,13 +804,13 @@ def main():
                 "hbm_gbs": bytes_launch / avg / 1e9}
 
     ttt = None
-    if not args.no_ttt and w.name == "c3":
+    if args.ttt and w.name == "c3":
         del B
         torch.cuda.empty_cache()
         ttt, _p1 = default_time_to_tol(checks)
 
     serving = None
-    if not args.no_serve:
+    if args.serve:
         log("[stage] serving stream")
         serving = serving_run(checks)
 

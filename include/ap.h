@@ -175,18 +175,6 @@ ap_status ap_epoch(const ap_handle* h, const ap_state* st, int32_t count, int32_
  * otherwise). The cached factors do not depend on the mode. */
 ap_status ap_set_tile(ap_handle h, int32_t tile);
 
-/* Cyclic look-ahead (Section 3, "Complexity": the chain of block updates is
- * sequential): epochs of this handle (ap_epoch, ap_solve, ap_solve_from) take
- * the blocks in groups of `blocks` consecutive ones (1 <= blocks <= 8; 1, the
- * default, is no look-ahead). Within a group each block's step is solved from
- * its rows of R, kept current by a pass over the group's rows after every
- * solve; one pass then updates every other row with the group's columns and
- * steps. W and R are those of the same block updates one after another, up to
- * the order of the sums, with one pass over the n rows per group. Needs
- * AP_CYCLIC and b a multiple of 64 (else AP_ERR_UNSUPPORTED); batch steps
- * and ap_update do not use it. */
-ap_status ap_set_lookahead(ap_handle h, int32_t blocks);
-
 /* One block update on block `block` (0 <= block < m): the inner loop body of
  * Algorithm 1. Asynchronous. */
 ap_status ap_update(ap_handle h, const ap_state* st, int32_t block, hipStream_t stream);

@@ -29,8 +29,7 @@ SYMBOLS = ("ap_workspace_bytes", "ap_factor_blocks", "ap_reset", "ap_epoch", "ap
            "ap_rel_residual", "ap_solve", "ap_solve_from", "ap_warm_start", "ap_residual", "ap_block_inverse", "ap_set_tile",
            "ap_profile",
            "ap_profile_read", "ap_predict", "ap_mll_grad", "ap_batch_step", "ap_batch_peek", "ap_batch_release",
-           "ap_destroy", "ap_status_str", "ap_last_error", "ap_residual_noalloc",
-           "ap_set_lookahead")
+           "ap_destroy", "ap_status_str", "ap_last_error", "ap_residual_noalloc")
 NOALLOC_MAX_N = 4194304
 PHASES = ("block_solve", "fused_update", "select", "epoch_check", "true_residual")
 
@@ -133,7 +132,6 @@ def load():
             "ap_predict": (I32, [P, P, P, I64, P, P]),
             "ap_mll_grad": (I32, [P, S, D, P, P]),
             "ap_set_tile": (I32, [P, I32]),
-            "ap_set_lookahead": (I32, [P, I32]),
             "ap_profile": (I32, [P, I32]),
             "ap_profile_read": (I32, [P, P, D, ctypes.POINTER(I64)]),
             "ap_batch_step": (I32, [ctypes.POINTER(P), S, I32, I32, P]),
@@ -314,10 +312,6 @@ class Solver:
 
     def set_tile(self, tile: int):
         _check(load().ap_set_tile(self.handle, int(tile)), "ap_set_tile")
-
-    def set_lookahead(self, blocks: int):
-        """Cyclic look-ahead: epochs take the blocks in groups of `blocks`."""
-        _check(load().ap_set_lookahead(self.handle, int(blocks)), "ap_set_lookahead")
 
     def profile(self, enable: bool = True):
         _check(load().ap_profile(self.handle, int(bool(enable))), "ap_profile")

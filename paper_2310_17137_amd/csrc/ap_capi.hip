@@ -29,9 +29,7 @@ struct ap_problem {
   // stream; re-captured when the state buffers or the tile mode change
   hipStream_t cap = nullptr;
   hipGraphExec_t epoch_exec = nullptr;
-  const void* key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  // blocks per look-ahead group of a cyclic epoch (1: none); ap_set_lookahead
-  int32_t look = 1;
+  const void* key[4] = {nullptr, nullptr, nullptr, nullptr};
   // batch steps: the descriptor grouped launches read (host copy and its place
   // in the workspace), and a stream plus pinned buffer for progress snapshots
   ap::Desc desc;
@@ -173,58 +171,8 @@ ap_status refine(ap_problem* h, const ap_state* st, hipStream_t s) {
   return AP_OK;
 }
 
-// The fused update of one span (plain block update when sp is nullptr).
-ap_status span_update(ap_problem* h, const ap_state* st, int32_t block, bool rowsq, bool colsq,
-                      const ap::Span* sp, hipStream_t s) {
-  if (h->L.tile == AP_TILE_FP64)
-    AP_PHASE(kUpdate, ap::launch_fused_update64(h->L, h->D, h->P, h->X, block, st->R, rowsq,
-                                                colsq, s, sp));
-  else
-    AP_PHASE(kUpdate, ap::launch_fused_update(h->L, h->D, block, st->R, rowsq, colsq, s, sp));
-  return AP_OK;
-}
-
-// A cyclic epoch with look-ahead (Section 3, "Complexity": the block updates
-// form a sequential chain). The blocks go in groups of h->look consecutive
-// ones. Within a group each block's step is solved from its rows of R, which
-// a narrow pass over the group's rows keeps current after every solve (the
-// block's own rows set to 0, the group's other rows updated by K^ times the
-// step); then one wide pass takes the whole group's columns and steps and
-// updates every row outside the group. R and W are then those of the group's
-// updates one after another, up to the order of the sums, with one pass over
-// the n rows per group instead of one per block.
-ap_status enqueue_epoch_look(ap_problem* h, const ap_state* st, hipStream_t s) {
-  const ap::Layout& L = h->L;
-  for (int32_t j0 = 0; j0 < L.m; j0 += h->look) {
-    const int32_t kk = std::min<int32_t>(h->look, L.m - j0);
-    const bool last = j0 + kk >= L.m;
-    if (kk == 1) {
-      ap_status r = one_update(h, st, j0, last, s);
-      if (r != AP_OK) return r;
-      continue;
-    }
-    const int64_t g0 = (int64_t)j0 * L.b;
-    const int64_t g1 = std::min<int64_t>((int64_t)(j0 + kk) * L.b, L.n);
-    for (int32_t j = 0; j < kk; ++j) {
-      const int64_t c0 = (int64_t)(j0 + j) * L.b;
-      const int32_t len = (int32_t)std::min<int64_t>(L.b, L.n - c0);
-      AP_PHASE(kSolve, ap::launch_block_solve(L, h->D, h->P, j0 + j, st->R, st->W, s, j * L.b));
-      const ap::Span local{c0, len, j * L.b, g0 / ap::kRowsWG * ap::kRowsWG, g0, g1, c0,
-                           c0 + len, 0, 0};
-      ap_status r = span_update(h, st, j0 + j, false, false, &local, s);
-      if (r != AP_OK) return r;
-    }
-    const ap::Span wide{g0, (int32_t)(g1 - g0), 0, 0, 0, L.n, 0, 0, g0, g1};
-    ap_status r = span_update(h, st, j0, false, last, &wide, s);
-    if (r != AP_OK) return r;
-  }
-  AP_PHASE(kCheck, ap::launch_epoch_check(L, h->D, s));
-  return AP_OK;
-}
-
 ap_status enqueue_epoch(ap_problem* h, const ap_state* st, hipStream_t s) {
   const bool cyclic = h->L.order == AP_CYCLIC;
-  if (cyclic && h->look > 1) return enqueue_epoch_look(h, st, s);
   for (int32_t u = 0; u < h->L.m; ++u) {
     ap_status r = one_update(h, st, cyclic ? u : -1, u == h->L.m - 1, s);
     if (r != AP_OK) return r;
@@ -243,8 +191,7 @@ void drop_graph(ap_problem* h) {
 // graph and replayed; with profiling on, the launches go out one by one.
 ap_status run_epoch(ap_problem* h, const ap_state* st, hipStream_t s) {
   if (h->prof) return enqueue_epoch(h, st, s);
-  const void* key[5] = {st->B, st->W, st->R, (const void*)(intptr_t)(h->L.tile + 1),
-                        (const void*)(intptr_t)h->look};
+  const void* key[4] = {st->B, st->W, st->R, (const void*)(intptr_t)(h->L.tile + 1)};
   if (!h->epoch_exec || std::memcmp(key, h->key, sizeof(key)) != 0) {
     drop_graph(h);
     if (!h->cap) AP_HIP(hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking));
@@ -537,13 +484,6 @@ ap_status ap_solve(ap_handle h, const ap_state* st, hipStream_t stream, ap_stats
 
 ap_status ap_solve_from(ap_handle h, const ap_state* st, hipStream_t stream, ap_stats* out) {
   return solve_impl(h, st, stream, out, true);
-}
-
-ap_status ap_set_lookahead(ap_handle h, int32_t blocks) {
-  if (!valid_handle(h) || blocks < 1 || blocks > ap::kLookMax) return AP_ERR_INVALID_ARG;
-  if (blocks > 1 && (h->L.order != AP_CYCLIC || h->L.b % ap::kT != 0)) return AP_ERR_UNSUPPORTED;
-  h->look = blocks;
-  return AP_OK;
 }
 
 ap_status ap_set_tile(ap_handle h, int32_t tile) {

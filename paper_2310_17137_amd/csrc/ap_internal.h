@@ -19,9 +19,6 @@ constexpr int kT = 64;
 // K-split of the FP64 block solve.
 constexpr int kBsSplit = 16;
 constexpr int kMaxD = 20;
-// Blocks of one look-ahead group (cyclic order): the step buffers hold this
-// many blocks' steps side by side.
-constexpr int kLookMax = 8;
 
 // Device control block at the start of the workspace.
 struct Ctl {
@@ -92,7 +89,6 @@ constexpr double kLog2e = 1.4426950408889634;
 struct Layout {
   int64_t n, n_pad;      // n_pad >= n + 32, multiple of kRowsWG
   int32_t d, l, b, m, b_pad, last_len;
-  int32_t dcap;          // columns of the step buffers: kLookMax b_pad
   int32_t kernel, order, tile;
   unsigned long long seed;  // random order: seed of the block draws
   int32_t ks;            // BF16 K-steps of 16 feature slots (3d + 6 slots)
@@ -114,7 +110,7 @@ struct Dev {  // device pointers into one problem's workspace
   double* kinv;          // m x b_pad x b_pad
   double* dinv;          // factor scratch: m x (b_pad/64) x 64 x 64
   double* panel;         // factor scratch: m x (b_pad/64) x 64 x 64
-  double* delta;         // dcap x 32 FP64 block steps (a look-ahead group side by side)
+  double* delta;         // b_pad x 32 FP64 block step
   double* bspart;        // kBsSplit x b_pad x 32 partial products
   void* dtile;           // block step as the fused update's MFMA operand
   float* rowsq;          // n_pad per-row sums of squares of R (greedy order)
@@ -140,51 +136,6 @@ struct Desc {
   double tol;
   int32_t min_epochs, max_epochs, refine_every, pad;
 };
-
-// Columns and rows of one fused-update launch. The default (clen == 0) is the
-// plain block update: the block's columns, every row, the block's own rows set
-// to 0. A look-ahead group (cyclic order) gives its own: the columns
-// [cstart, cstart + clen) with their steps at column coff of the step
-// buffers; rows from rbase (the launch's first row); rows outside [w0, w1)
-// untouched and left out of the norms; rows in [z0, z1) set to 0; rows in
-// [k0, k1) kept as they are (but counted in the norms).
-struct Span {
-  int64_t cstart;
-  int32_t clen, coff;
-  int64_t rbase, w0, w1, z0, z1, k0, k1;
-};
-
-// The span of a launch: the given one, or the plain update of block blk.
-__device__ __forceinline__ Span block_span(const Layout& L, int blk, const Span& given) {
-  if (given.clen > 0) return given;
-  Span s;
-  s.cstart = (int64_t)blk * L.b;
-  s.clen = (int32_t)(L.n - s.cstart < L.b ? L.n - s.cstart : L.b);
-  s.coff = 0;
-  s.rbase = 0;
-  s.w0 = 0;
-  s.w1 = L.n;
-  s.z0 = s.cstart;
-  s.z1 = s.cstart + s.clen;
-  s.k0 = s.k1 = 0;
-  return s;
-}
-
-// Workgroups of a fused-update launch: every row (the partials of the
-// epoch-end check are per workgroup) unless the span covers only some rows.
-inline int span_grid(const Layout& L, const Span* sp) {
-  if (!sp || sp->w0 == 0) return L.nwg;
-  return (int)((sp->w1 - sp->rbase + kRowsWG - 1) / kRowsWG);
-}
-
-// What a launch does to row `row` of its span: 0 not touched, 1 set to 0,
-// 2 kept, 3 updated (R - the product).
-__device__ __forceinline__ int row_role(const Span& s, int64_t row) {
-  if (row < s.w0 || row >= s.w1) return 0;
-  if (row >= s.z0 && row < s.z1) return 1;
-  if (row >= s.k0 && row < s.k1) return 2;
-  return 3;
-}
 
 // Problems of one grouped launch: workgroups [wg0[p], wg0[p+1]) serve problem p.
 constexpr int kMaxBatch = 32;
@@ -232,16 +183,13 @@ hipError_t launch_bnorm(const Layout& L, const Dev& D, const float* B, hipStream
 // workgroups of the true residual over n rows (its column partials in D.respart)
 int residual_groups(int64_t n);
 // block: >= 0, kBlockSel or a batch code (see resolve_block)
-// the step goes to column coff of the step buffers (0 unless in a look-ahead group)
 hipError_t launch_block_solve(const Layout& L, const Dev& D, const Params& P, int32_t block,
-                              const float* R, double* W, hipStream_t st, int32_t coff = 0);
-// sp: nullptr for the plain block update, else a look-ahead span (grid from it)
+                              const float* R, double* W, hipStream_t st);
 hipError_t launch_fused_update(const Layout& L, const Dev& D, int32_t block, float* R,
-                               bool want_rowsq, bool want_colsq, hipStream_t st,
-                               const Span* sp = nullptr);
+                               bool want_rowsq, bool want_colsq, hipStream_t st);
 hipError_t launch_fused_update64(const Layout& L, const Dev& D, const Params& P, const float* X,
                                  int32_t block, float* R, bool want_rowsq, bool want_colsq,
-                                 hipStream_t st, const Span* sp = nullptr);
+                                 hipStream_t st);
 hipError_t launch_select(const Layout& L, const Dev& D, hipStream_t st);
 hipError_t launch_epoch_check(const Layout& L, const Dev& D, hipStream_t st);
 hipError_t launch_residual(const Layout& L, const Dev& D, const Params& P, const float* X,

@@ -21,7 +21,6 @@ bool make_layout(int64_t n, int32_t d, int32_t l, int32_t b, int32_t kernel, int
   o.b = b;
   o.m = (int32_t)((n + b - 1) / b);
   o.b_pad = (b + kT - 1) / kT * kT;
-  o.dcap = kLookMax * o.b_pad;
   o.last_len = (int32_t)(n - (int64_t)(o.m - 1) * b);
   o.kernel = kernel;
   o.order = order;
@@ -46,9 +45,9 @@ bool make_layout(int64_t n, int32_t d, int32_t l, int32_t b, int32_t kernel, int
   o.off_kinv = take((size_t)o.m * o.b_pad * o.b_pad * sizeof(double));
   o.off_dinv = take((size_t)o.m * o.b_pad * kT * sizeof(double));
   o.off_panel = take((size_t)o.m * o.b_pad * kT * sizeof(double));
-  o.off_delta = take((size_t)o.dcap * kMaxL * sizeof(double));
+  o.off_delta = take((size_t)o.b_pad * kMaxL * sizeof(double));
   o.off_bspart = take((size_t)kBsSplit * o.b_pad * kMaxL * sizeof(double));
-  o.off_dtile = take((size_t)o.dcap * 2 * kMaxL * sizeof(float));
+  o.off_dtile = take((size_t)o.b_pad * 2 * kMaxL * sizeof(float));
   o.off_rowsq = take((size_t)o.n_pad * sizeof(float));
   o.off_colsq = take((size_t)o.nwg * kMaxL * sizeof(float));
   o.off_blocknorm = take((size_t)o.m * sizeof(double));

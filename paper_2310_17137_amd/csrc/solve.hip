@@ -85,28 +85,24 @@ __global__ __launch_bounds__(256) void k_bs_partial(Layout L, const double* __re
 }
 
 // Sum the slices in a fixed order, update W_I, keep delta in FP64 and write
-// s * delta in the fused update's operand layout (element e = i * 32 + c), at
-// column coff + i of the step buffers (coff: the block's place in a look-ahead
-// group, 0 otherwise; rows i in [len, b_pad) are written as 0).
+// s * delta in the fused update's operand layout (element e = i * 32 + c).
 __device__ __forceinline__ void bs_finish_body(const Layout& L, int blk, int tile, double s,
                                                const double* __restrict__ part,
                                                double* __restrict__ W,
-                                               double* __restrict__ delta, void* dtile, int e,
-                                               int coff) {
+                                               double* __restrict__ delta, void* dtile, int e) {
   const int64_t start = (int64_t)blk * L.b;
   const int len = (int)std::min<int64_t>(L.b, L.n - start);
   if (e >= L.b_pad * kMaxL) return;
-  const int i0 = e / kMaxL, c = e % kMaxL;
+  const int i = e / kMaxL, c = e % kMaxL;
   double v = 0.0;
-  if (i0 < len && c < L.l) {
-    for (int sp = 0; sp < kBsSplit; ++sp) v += part[((size_t)sp * L.b_pad + i0) * kMaxL + c];
-    W[(start + i0) * L.l + c] += v;
+  if (i < len && c < L.l) {
+    for (int sp = 0; sp < kBsSplit; ++sp) v += part[((size_t)sp * L.b_pad + i) * kMaxL + c];
+    W[(start + i) * L.l + c] += v;
   }
-  const int i = coff + i0;
-  delta[(size_t)i * kMaxL + c] = v;
+  delta[i * kMaxL + c] = v;
   if (tile == 3) return;  // the FP64-tile update reads delta itself
   if (tile == 0) {
-    ((float*)dtile)[(size_t)i * kMaxL + c] = (float)(s * v);
+    ((float*)dtile)[i * kMaxL + c] = (float)(s * v);
     return;
   }
   // BF16 operand layout: bcol i of chunk ch sits in k-step st = w / 16 at
@@ -121,7 +117,7 @@ __device__ __forceinline__ void bs_finish_body(const Layout& L, int blk, int til
     return;
   }
   // split path: s * delta = h + m + l, three BF16 terms (24 significant bits)
-  const size_t term = (size_t)L.dcap * kMaxL;
+  const size_t term = (size_t)L.b_pad * kMaxL;
   const double sv = s * v;
   const uint16_t h = bf16_rne((float)sv);
   const double r1 = sv - (double)bf16_to_f32(h);
@@ -136,12 +132,10 @@ __global__ __launch_bounds__(256) void k_bs_finish(Layout L, const Ctl* __restri
                                                    int block, double s,
                                                    const double* __restrict__ part,
                                                    double* __restrict__ W,
-                                                   double* __restrict__ delta, void* dtile,
-                                                   int coff) {
+                                                   double* __restrict__ delta, void* dtile) {
   const int blk = resolve_block(block, ctl, L.m);
   if (blk < 0) return;
-  bs_finish_body(L, blk, L.tile, s, part, W, delta, dtile, (int)blockIdx.x * 256 + threadIdx.x,
-                 coff);
+  bs_finish_body(L, blk, L.tile, s, part, W, delta, dtile, (int)blockIdx.x * 256 + threadIdx.x);
 }
 
 // Grouped forms for a batch step: every workgroup finds its problem in the
@@ -181,13 +175,13 @@ __global__ __launch_bounds__(256) void g_bs_finish(Group g) {
   const int blk = resolve_block(batch_code(L), ds->D.ctl, L.m);
   if (blk < 0) return;
   bs_finish_body(L, blk, g.tile[p], ds->P.s, ds->D.bspart, g.W[p], ds->D.delta, ds->D.dtile,
-                 wg * 256 + threadIdx.x, 0);
+                 wg * 256 + threadIdx.x);
 }
 
 }  // namespace
 
 hipError_t launch_block_solve(const Layout& L, const Dev& D, const Params& P, int32_t block,
-                              const float* R, double* W, hipStream_t st, int32_t coff) {
+                              const float* R, double* W, hipStream_t st) {
   const int ntile = L.b_pad / 64;
   const dim3 g(ntile * kBsSplit), t(256);
   if (L.l <= 1)
@@ -202,7 +196,7 @@ hipError_t launch_block_solve(const Layout& L, const Dev& D, const Params& P, in
     hipLaunchKernelGGL(k_bs_partial<32>, g, t, 0, st, L, D.kinv, D.ctl, block, R, D.bspart);
   const int tot = L.b_pad * kMaxL;
   hipLaunchKernelGGL(k_bs_finish, dim3((tot + 255) / 256), dim3(256), 0, st, L, D.ctl, block,
-                     P.s, D.bspart, W, D.delta, D.dtile, (int)coff);
+                     P.s, D.bspart, W, D.delta, D.dtile);
   return hipGetLastError();
 }
 

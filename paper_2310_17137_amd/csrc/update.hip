@@ -146,7 +146,7 @@ __device__ __forceinline__ bf16x8 pack8(const f32x16& v, int base) {
 // Epilogue shared by both tile precisions. acc[t][v] holds, for data row
 // row0 + 32 t + lane % 32, the update of column m = 8 (v / 4) + 4 (lane / 32) + v % 4.
 template <typename Acc>
-__device__ __forceinline__ void epilogue(const Layout& L, int64_t row0, const Span& S,
+__device__ __forceinline__ void epilogue(const Layout& L, int64_t row0, int64_t start, int len,
                                          const Acc acc[2], float* __restrict__ R,
                                          float* __restrict__ rowsq, float* __restrict__ colsq,
                                          bool want_rowsq, bool want_colsq, int wg) {
@@ -160,23 +160,22 @@ __device__ __forceinline__ void epilogue(const Layout& L, int64_t row0, const Sp
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const int64_t row = row0 + 32 * t + nl;
-    const int role = row_role(S, row);
+    const bool in_i = row >= start && row < start + len;
+    const bool live = row < L.n;
     float rs = 0.f;
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const int m = 8 * (v / 4) + 4 * g + (v % 4);
-      if (role != 0 && m < l) {
-        const float r = role == 1 ? 0.f
-                        : role == 2 ? R[row * l + m]
-                                    : (float)(R[row * l + m] - acc[t][v]);
-        if (role != 2) R[row * l + m] = r;
+      if (live && m < l) {
+        float r = in_i ? 0.f : (float)(R[row * l + m] - acc[t][v]);
+        R[row * l + m] = r;
         rs = fmaf(r, r, rs);
         csum[v] = fmaf(r, r, csum[v]);
       }
     }
     if (want_rowsq) {
       rs += __shfl_xor(rs, 32);
-      if (g == 0 && row < L.n_pad && (role != 0 || row >= L.n)) rowsq[row] = role != 0 ? rs : 0.f;
+      if (g == 0 && row < L.n_pad) rowsq[row] = live ? rs : 0.f;
     }
   }
   if (want_colsq) {
@@ -209,19 +208,18 @@ __global__ __launch_bounds__(256) void k_fused_bf16(Layout L, const uint16_t* __
                                                     const uint16_t* __restrict__ xcol,
                                                     const uint16_t* __restrict__ dtile,
                                                     const Ctl* __restrict__ ctl, int block,
-                                                    Span sp, float* __restrict__ R,
+                                                    float* __restrict__ R,
                                                     float* __restrict__ rowsq,
                                                     float* __restrict__ colsq, int want_rowsq,
                                                     int want_colsq) {
   const int blk = resolve_block(block, ctl, L.m);
   if (blk < 0) return;
-  const Span S = block_span(L, blk, sp);
-  const int64_t start = S.cstart;
-  const int nch = (S.clen + kChunk - 1) / kChunk;
+  const int64_t start = (int64_t)blk * L.b;
+  const int len = (int)std::min<int64_t>(L.b, L.n - start);
+  const int nch = (len + kChunk - 1) / kChunk;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int nl = lane % 32, g = lane / 32;
-  const int64_t row0 = S.rbase + (int64_t)blockIdx.x * kRowsWG + wave * 64;
-  const size_t ch0 = S.coff / kChunk;
+  const int64_t row0 = (int64_t)blockIdx.x * kRowsWG + wave * 64;
   constexpr int KF = 16 * KS;
 
   bf16x8 brow[2][KS];
@@ -242,8 +240,8 @@ __global__ __launch_bounds__(256) void k_fused_bf16(Layout L, const uint16_t* __
     bf16x8 acol[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) acol[ks] = load_bf16x8(xcol + (cb + nl) * KF + 16 * ks + 8 * g);
-    const bf16x8 d0 = load_bf16x8(dtile + (((ch0 + ch) * 2 + 0) * 64 + lane) * 8);
-    const bf16x8 d1 = load_bf16x8(dtile + (((ch0 + ch) * 2 + 1) * 64 + lane) * 8);
+    const bf16x8 d0 = load_bf16x8(dtile + (((size_t)ch * 2 + 0) * 64 + lane) * 8);
+    const bf16x8 d1 = load_bf16x8(dtile + (((size_t)ch * 2 + 1) * 64 + lane) * 8);
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
       f32x16 s;
@@ -258,7 +256,7 @@ __global__ __launch_bounds__(256) void k_fused_bf16(Layout L, const uint16_t* __
       acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(d1, pack8(s, 8), acc[t], 0, 0, 0);
     }
   }
-  epilogue(L, row0, S, acc, R, rowsq, colsq, want_rowsq, want_colsq, (int)blockIdx.x);
+  epilogue(L, row0, start, len, acc, R, rowsq, colsq, want_rowsq, want_colsq, (int)blockIdx.x);
 }
 
 // FP32 tiles: the prepared features in FP64, the squared distance in FP64, the
@@ -269,7 +267,7 @@ template <int KERN, int DV, int DP>
 __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const double* __restrict__ xv,
                                                     const float* __restrict__ dtile,
                                                     const Ctl* __restrict__ ctl, int block,
-                                                    Span sp, float* __restrict__ R,
+                                                    float* __restrict__ R,
                                                     float* __restrict__ rowsq,
                                                     float* __restrict__ colsq, int want_rowsq,
                                                     int want_colsq) {
@@ -278,12 +276,12 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const double* __re
   __shared__ float sd[kChunk][kMaxL];
   const int blk = resolve_block(block, ctl, L.m);
   if (blk < 0) return;
-  const Span S = block_span(L, blk, sp);
-  const int64_t start = S.cstart;
-  const int nch = (S.clen + kChunk - 1) / kChunk;
+  const int64_t start = (int64_t)blk * L.b;
+  const int len = (int)std::min<int64_t>(L.b, L.n - start);
+  const int nch = (len + kChunk - 1) / kChunk;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int nl = lane % 32, g = lane / 32;
-  const int64_t row0 = S.rbase + (int64_t)blockIdx.x * kRowsWG + wave * 64;
+  const int64_t row0 = (int64_t)blockIdx.x * kRowsWG + wave * 64;
 
   double xr[2][DV], nr[2];
 #pragma unroll
@@ -306,7 +304,7 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const double* __re
     __syncthreads();
     stage_cols<DV, DP>(xv, cb, &sx[0][0], sn);
     for (int e = threadIdx.x; e < kChunk * kMaxL; e += 256)
-      (&sd[0][0])[e] = dtile[((int64_t)S.coff + ch * kChunk) * kMaxL + e];
+      (&sd[0][0])[e] = dtile[(int64_t)ch * kChunk * kMaxL + e];
     __syncthreads();
     f32x16 part[2];
 #pragma unroll
@@ -332,7 +330,7 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const double* __re
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[t][v] += (double)part[t][v];
   }
-  epilogue(L, row0, S, acc, R, rowsq, colsq, want_rowsq, want_colsq, (int)blockIdx.x);
+  epilogue(L, row0, start, len, acc, R, rowsq, colsq, want_rowsq, want_colsq, (int)blockIdx.x);
 }
 
 // FP32 tiles with few right-hand sides (l <= 8): the product with the step on
@@ -346,7 +344,7 @@ template <int KERN, int DV, int DP, int NV>
 __global__ __launch_bounds__(256) void k_fused_fp32v(Layout L, const double* __restrict__ xv,
                                                      const float* __restrict__ dtile,
                                                      const Ctl* __restrict__ ctl, int block,
-                                                     Span sp, float* __restrict__ R,
+                                                     float* __restrict__ R,
                                                      float* __restrict__ rowsq,
                                                      float* __restrict__ colsq, int want_rowsq,
                                                      int want_colsq) {
@@ -356,12 +354,12 @@ __global__ __launch_bounds__(256) void k_fused_fp32v(Layout L, const double* __r
   __shared__ float red[4][NV];
   const int blk = resolve_block(block, ctl, L.m);
   if (blk < 0) return;
-  const Span S = block_span(L, blk, sp);
-  const int64_t start = S.cstart;
-  const int nch = (S.clen + kChunk - 1) / kChunk;
+  const int64_t start = (int64_t)blk * L.b;
+  const int len = (int)std::min<int64_t>(L.b, L.n - start);
+  const int nch = (len + kChunk - 1) / kChunk;
   const int l = L.l;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-  const int64_t row = S.rbase + (int64_t)blockIdx.x * kRowsWG + threadIdx.x;
+  const int64_t row = (int64_t)blockIdx.x * kRowsWG + threadIdx.x;
 
   double xr[DV];
 #pragma unroll
@@ -376,7 +374,7 @@ __global__ __launch_bounds__(256) void k_fused_fp32v(Layout L, const double* __r
     __syncthreads();
     stage_cols<DV, DP>(xv, cb, &sx[0][0], sn);
     for (int e = threadIdx.x; e < kChunk * NV; e += 256)
-      sd[e / NV][e % NV] = dtile[((int64_t)S.coff + ch * kChunk + e / NV) * kMaxL + e % NV];
+      sd[e / NV][e % NV] = dtile[((int64_t)ch * kChunk + e / NV) * kMaxL + e % NV];
     __syncthreads();
     float part[NV];
 #pragma unroll
@@ -391,21 +389,20 @@ __global__ __launch_bounds__(256) void k_fused_fp32v(Layout L, const double* __r
     for (int c = 0; c < NV; ++c) acc[c] += (double)part[c];
   }
 
-  const int role = row_role(S, row);
+  const bool live = row < L.n;
+  const bool in_i = row >= start && row < start + len;
   float rs = 0.f, csq[NV];
 #pragma unroll
   for (int c = 0; c < NV; ++c) {
     csq[c] = 0.f;
-    if (role != 0 && c < l) {
-      const float r = role == 1 ? 0.f
-                      : role == 2 ? R[row * l + c]
-                                  : (float)((double)R[row * l + c] - acc[c]);
-      if (role != 2) R[row * l + c] = r;
+    if (live && c < l) {
+      const float r = in_i ? 0.f : (float)((double)R[row * l + c] - acc[c]);
+      R[row * l + c] = r;
       rs = fmaf(r, r, rs);
       csq[c] = r * r;
     }
   }
-  if (want_rowsq && row < L.n_pad && (role != 0 || row >= L.n)) rowsq[row] = role != 0 ? rs : 0.f;
+  if (want_rowsq && row < L.n_pad) rowsq[row] = live ? rs : 0.f;
   if (want_colsq) {
 #pragma unroll
     for (int c = 0; c < NV; ++c) {
@@ -438,17 +435,17 @@ __global__ __launch_bounds__(256) void k_fused_fp32v(Layout L, const double* __r
 // built per lane in the BF16 path's column order, so the step layout is shared.
 template <int KERN, int DV, int DP>
 __device__ __forceinline__ void split_body(const Layout& L, const double* __restrict__ xv,
-                                           const uint16_t* __restrict__ dtile, const Span& S,
+                                           const uint16_t* __restrict__ dtile, int blk,
                                            float* __restrict__ R, float* __restrict__ rowsq,
                                            float* __restrict__ colsq, bool want_rowsq,
                                            bool want_colsq, int wg, double* sx) {
-  const int64_t start = S.cstart;
-  const int nch = (S.clen + kChunk - 1) / kChunk;
+  const int64_t start = (int64_t)blk * L.b;
+  const int len = (int)std::min<int64_t>(L.b, L.n - start);
+  const int nch = (len + kChunk - 1) / kChunk;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int nl = lane % 32, g = lane / 32;
-  const int64_t row0 = S.rbase + (int64_t)wg * kRowsWG + wave * 64;
-  const size_t term = (size_t)L.dcap * kMaxL;
-  const size_t ch0 = S.coff / kChunk;
+  const int64_t row0 = (int64_t)wg * kRowsWG + wave * 64;
+  const size_t term = (size_t)L.b_pad * kMaxL;
 
   double xr[2][DV];
 #pragma unroll
@@ -474,7 +471,7 @@ __device__ __forceinline__ void split_body(const Layout& L, const double* __rest
       for (int v = 0; v < 16; ++v) part[t][v] = 0.f;
 #pragma unroll
     for (int st = 0; st < 2; ++st) {
-      const size_t at = (((ch0 + ch) * 2 + st) * 64 + lane) * 8;
+      const size_t at = (((size_t)ch * 2 + st) * 64 + lane) * 8;
       const bf16x8 dh = load_bf16x8(dtile + at);
       const bf16x8 dm = load_bf16x8(dtile + term + at);
       const bf16x8 dl = load_bf16x8(dtile + 2 * term + at);
@@ -506,22 +503,22 @@ __device__ __forceinline__ void split_body(const Layout& L, const double* __rest
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[t][v] += (double)part[t][v];
   }
-  epilogue(L, row0, S, acc, R, rowsq, colsq, want_rowsq, want_colsq, wg);
+  epilogue(L, row0, start, len, acc, R, rowsq, colsq, want_rowsq, want_colsq, wg);
 }
 
 template <int KERN, int DV, int DP>
 __global__ __launch_bounds__(256) void k_fused_split(Layout L, const double* __restrict__ xv,
                                                      const uint16_t* __restrict__ dtile,
                                                      const Ctl* __restrict__ ctl, int block,
-                                                     Span sp, float* __restrict__ R,
+                                                     float* __restrict__ R,
                                                      float* __restrict__ rowsq,
                                                      float* __restrict__ colsq, int want_rowsq,
                                                      int want_colsq) {
   __shared__ double sx[kChunk * DP];
   const int blk = resolve_block(block, ctl, L.m);
   if (blk < 0) return;
-  split_body<KERN, DV, DP>(L, xv, dtile, block_span(L, blk, sp), R, rowsq, colsq, want_rowsq,
-                           want_colsq, (int)blockIdx.x, sx);
+  split_body<KERN, DV, DP>(L, xv, dtile, blk, R, rowsq, colsq, want_rowsq, want_colsq,
+                           (int)blockIdx.x, sx);
 }
 
 // Grouped split update of a batch step: each workgroup runs the body for its
@@ -531,22 +528,21 @@ __global__ __launch_bounds__(256) void k_fused_split(Layout L, const double* __r
 template <int KERN, int WIDE>
 __device__ __forceinline__ void split_dispatch(const Layout& L, const Desc* ds, int blk, float* R,
                                                int wg, double* sx) {
-  const Span S = block_span(L, blk, Span{});
   const double* xs = ds->D.xv;
   const uint16_t* dt = (const uint16_t*)ds->D.dtile;
   const bool wr = L.order == 1;
   if constexpr (WIDE == 0) {
     if (L.dp == 4)
-      split_body<KERN, 4, 4>(L, xs, dt, S, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx);
+      split_body<KERN, 4, 4>(L, xs, dt, blk, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx);
     else
-      split_body<KERN, 8, 8>(L, xs, dt, S, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx);
+      split_body<KERN, 8, 8>(L, xs, dt, blk, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx);
   } else {
     if (L.dp == 12)
-      split_body<KERN, 12, 12>(L, xs, dt, S, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx);
+      split_body<KERN, 12, 12>(L, xs, dt, blk, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx);
     else if (L.dp == 16)
-      split_body<KERN, 16, 16>(L, xs, dt, S, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx);
+      split_body<KERN, 16, 16>(L, xs, dt, blk, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx);
     else
-      split_body<KERN, 20, 20>(L, xs, dt, S, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx);
+      split_body<KERN, 20, 20>(L, xs, dt, blk, R, ds->D.rowsq, ds->D.colsq, wr, true, wg, sx);
   }
 }
 
@@ -573,15 +569,14 @@ __global__ __launch_bounds__(256) void g_fused_split(Group g) {
 
 template <int KERN>
 hipError_t launch_bf16(const Layout& L, const Dev& D, int32_t block, float* R, bool wr, bool wc,
-                       hipStream_t st, const Span* sp) {
-  const dim3 g(span_grid(L, sp)), t(256);
-  const Span S = sp ? *sp : Span{};
+                       hipStream_t st) {
+  const dim3 g(L.nwg), t(256);
   const uint16_t* dt = (const uint16_t*)D.dtile;
   switch (L.ks) {
-    case 1: hipLaunchKernelGGL((k_fused_bf16<KERN, 1>), g, t, 0, st, L, D.xrow, D.xcol, dt, D.ctl, block, S, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
-    case 2: hipLaunchKernelGGL((k_fused_bf16<KERN, 2>), g, t, 0, st, L, D.xrow, D.xcol, dt, D.ctl, block, S, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
-    case 3: hipLaunchKernelGGL((k_fused_bf16<KERN, 3>), g, t, 0, st, L, D.xrow, D.xcol, dt, D.ctl, block, S, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
-    case 4: hipLaunchKernelGGL((k_fused_bf16<KERN, 4>), g, t, 0, st, L, D.xrow, D.xcol, dt, D.ctl, block, S, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 1: hipLaunchKernelGGL((k_fused_bf16<KERN, 1>), g, t, 0, st, L, D.xrow, D.xcol, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 2: hipLaunchKernelGGL((k_fused_bf16<KERN, 2>), g, t, 0, st, L, D.xrow, D.xcol, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 3: hipLaunchKernelGGL((k_fused_bf16<KERN, 3>), g, t, 0, st, L, D.xrow, D.xcol, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 4: hipLaunchKernelGGL((k_fused_bf16<KERN, 4>), g, t, 0, st, L, D.xrow, D.xcol, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -589,13 +584,12 @@ hipError_t launch_bf16(const Layout& L, const Dev& D, int32_t block, float* R, b
 
 template <int KERN, int NV>
 hipError_t launch_fp32v(const Layout& L, const Dev& D, int32_t block, float* R, bool wr, bool wc,
-                        hipStream_t st, const Span* sp) {
-  const dim3 g(span_grid(L, sp)), t(256);
-  const Span S = sp ? *sp : Span{};
+                        hipStream_t st) {
+  const dim3 g(L.nwg), t(256);
   const float* dt = (const float*)D.dtile;
 #define AP_FP32V(DV, DP)                                                                  \
   hipLaunchKernelGGL((k_fused_fp32v<KERN, DV, DP, NV>), g, t, 0, st, L, D.xv, dt, D.ctl, \
-                     block, S, R, D.rowsq, D.colsq, (int)wr, (int)wc)
+                     block, R, D.rowsq, D.colsq, (int)wr, (int)wc)
   if (L.d == 3) {
     AP_FP32V(3, 4);
   } else {
@@ -614,16 +608,15 @@ hipError_t launch_fp32v(const Layout& L, const Dev& D, int32_t block, float* R, 
 
 template <int KERN>
 hipError_t launch_fp32(const Layout& L, const Dev& D, int32_t block, float* R, bool wr, bool wc,
-                       hipStream_t st, const Span* sp) {
-  if (L.l <= 1) return launch_fp32v<KERN, 1>(L, D, block, R, wr, wc, st, sp);
-  if (L.l <= 2) return launch_fp32v<KERN, 2>(L, D, block, R, wr, wc, st, sp);
-  if (L.l <= 4) return launch_fp32v<KERN, 4>(L, D, block, R, wr, wc, st, sp);
-  if (L.l <= 8) return launch_fp32v<KERN, 8>(L, D, block, R, wr, wc, st, sp);
-  const dim3 g(span_grid(L, sp)), t(256);
-  const Span S = sp ? *sp : Span{};
+                       hipStream_t st) {
+  if (L.l <= 1) return launch_fp32v<KERN, 1>(L, D, block, R, wr, wc, st);
+  if (L.l <= 2) return launch_fp32v<KERN, 2>(L, D, block, R, wr, wc, st);
+  if (L.l <= 4) return launch_fp32v<KERN, 4>(L, D, block, R, wr, wc, st);
+  if (L.l <= 8) return launch_fp32v<KERN, 8>(L, D, block, R, wr, wc, st);
+  const dim3 g(L.nwg), t(256);
   const float* dt = (const float*)D.dtile;
 #define AP_FP32(DV, DP)                                                                        \
-  hipLaunchKernelGGL((k_fused_fp32<KERN, DV, DP>), g, t, 0, st, L, D.xv, dt, D.ctl, block, S, R, \
+  hipLaunchKernelGGL((k_fused_fp32<KERN, DV, DP>), g, t, 0, st, L, D.xv, dt, D.ctl, block, R, \
                      D.rowsq, D.colsq, (int)wr, (int)wc)
   if (L.d == 3) {
     AP_FP32(3, 4);
@@ -643,20 +636,19 @@ hipError_t launch_fp32(const Layout& L, const Dev& D, int32_t block, float* R, b
 
 template <int KERN>
 hipError_t launch_split(const Layout& L, const Dev& D, int32_t block, float* R, bool wr,
-                        bool wc, hipStream_t st, const Span* sp) {
-  const dim3 g(span_grid(L, sp)), t(256);
-  const Span S = sp ? *sp : Span{};
+                        bool wc, hipStream_t st) {
+  const dim3 g(L.nwg), t(256);
   const uint16_t* dt = (const uint16_t*)D.dtile;
   if (L.d == 3) {
-    hipLaunchKernelGGL((k_fused_split<KERN, 3, 4>), g, t, 0, st, L, D.xv, dt, D.ctl, block, S, R, D.rowsq, D.colsq, (int)wr, (int)wc);
+    hipLaunchKernelGGL((k_fused_split<KERN, 3, 4>), g, t, 0, st, L, D.xv, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc);
     return hipGetLastError();
   }
   switch (L.dp) {
-    case 4: hipLaunchKernelGGL((k_fused_split<KERN, 4, 4>), g, t, 0, st, L, D.xv, dt, D.ctl, block, S, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
-    case 8: hipLaunchKernelGGL((k_fused_split<KERN, 8, 8>), g, t, 0, st, L, D.xv, dt, D.ctl, block, S, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
-    case 12: hipLaunchKernelGGL((k_fused_split<KERN, 12, 12>), g, t, 0, st, L, D.xv, dt, D.ctl, block, S, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
-    case 16: hipLaunchKernelGGL((k_fused_split<KERN, 16, 16>), g, t, 0, st, L, D.xv, dt, D.ctl, block, S, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
-    case 20: hipLaunchKernelGGL((k_fused_split<KERN, 20, 20>), g, t, 0, st, L, D.xv, dt, D.ctl, block, S, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 4: hipLaunchKernelGGL((k_fused_split<KERN, 4, 4>), g, t, 0, st, L, D.xv, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 8: hipLaunchKernelGGL((k_fused_split<KERN, 8, 8>), g, t, 0, st, L, D.xv, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 12: hipLaunchKernelGGL((k_fused_split<KERN, 12, 12>), g, t, 0, st, L, D.xv, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 16: hipLaunchKernelGGL((k_fused_split<KERN, 16, 16>), g, t, 0, st, L, D.xv, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
+    case 20: hipLaunchKernelGGL((k_fused_split<KERN, 20, 20>), g, t, 0, st, L, D.xv, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -673,25 +665,25 @@ hipError_t launch_group_split(const Group& g, bool wide, hipStream_t st) {
 }
 
 hipError_t launch_fused_update(const Layout& L, const Dev& D, int32_t block, float* R,
-                               bool want_rowsq, bool want_colsq, hipStream_t st, const Span* sp) {
+                               bool want_rowsq, bool want_colsq, hipStream_t st) {
   if (L.tile == 1) {
     switch (L.kernel) {
-      case 0: return launch_bf16<0>(L, D, block, R, want_rowsq, want_colsq, st, sp);
-      case 1: return launch_bf16<1>(L, D, block, R, want_rowsq, want_colsq, st, sp);
-      default: return launch_bf16<2>(L, D, block, R, want_rowsq, want_colsq, st, sp);
+      case 0: return launch_bf16<0>(L, D, block, R, want_rowsq, want_colsq, st);
+      case 1: return launch_bf16<1>(L, D, block, R, want_rowsq, want_colsq, st);
+      default: return launch_bf16<2>(L, D, block, R, want_rowsq, want_colsq, st);
     }
   }
   if (L.tile == 2) {
     switch (L.kernel) {
-      case 0: return launch_split<0>(L, D, block, R, want_rowsq, want_colsq, st, sp);
-      case 1: return launch_split<1>(L, D, block, R, want_rowsq, want_colsq, st, sp);
-      default: return launch_split<2>(L, D, block, R, want_rowsq, want_colsq, st, sp);
+      case 0: return launch_split<0>(L, D, block, R, want_rowsq, want_colsq, st);
+      case 1: return launch_split<1>(L, D, block, R, want_rowsq, want_colsq, st);
+      default: return launch_split<2>(L, D, block, R, want_rowsq, want_colsq, st);
     }
   }
   switch (L.kernel) {
-    case 0: return launch_fp32<0>(L, D, block, R, want_rowsq, want_colsq, st, sp);
-    case 1: return launch_fp32<1>(L, D, block, R, want_rowsq, want_colsq, st, sp);
-    default: return launch_fp32<2>(L, D, block, R, want_rowsq, want_colsq, st, sp);
+    case 0: return launch_fp32<0>(L, D, block, R, want_rowsq, want_colsq, st);
+    case 1: return launch_fp32<1>(L, D, block, R, want_rowsq, want_colsq, st);
+    default: return launch_fp32<2>(L, D, block, R, want_rowsq, want_colsq, st);
   }
 }
 

@@ -82,7 +82,7 @@ template <int KERN, int DV, int DP, int NH>
 __global__ __launch_bounds__(256) void k_fused_fp64(Layout L, Params P, const float* __restrict__ X,
                                                     const double* __restrict__ delta,
                                                     const Ctl* __restrict__ ctl, int block,
-                                                    Span sp, float* __restrict__ R,
+                                                    float* __restrict__ R,
                                                     float* __restrict__ rowsq,
                                                     float* __restrict__ colsq, int want_rowsq,
                                                     int want_colsq) {
@@ -94,13 +94,12 @@ __global__ __launch_bounds__(256) void k_fused_fp64(Layout L, Params P, const fl
   const int blk = resolve_block(block, ctl, L.m);
   if (blk < 0) return;
   scaled_exp_table(etab, P.s);  // visible after the first barrier of the chunk loop
-  const Span S = block_span(L, blk, sp);
-  const int64_t start = S.cstart;
-  const int len = S.clen;
+  const int64_t start = (int64_t)blk * L.b;
+  const int len = (int)std::min<int64_t>(L.b, L.n - start);
   const int d = L.d, l = L.l;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int ln = lane % 16, lg = lane / 16;
-  const int64_t row0 = S.rbase + (int64_t)blockIdx.x * kRowsWG + wave * 64;
+  const int64_t row0 = (int64_t)blockIdx.x * kRowsWG + wave * 64;
 
   double xi[4][DV], ni[4];
 #pragma unroll
@@ -116,7 +115,7 @@ __global__ __launch_bounds__(256) void k_fused_fp64(Layout L, Params P, const fl
     stage_cols64<DV, DP>(X, start, c0, len, d, P, ctl, sx, sn);
     for (int e = threadIdx.x; e < kCols64 * 16 * NH; e += 256) {
       const int jj = e / (16 * NH), c = e % (16 * NH);
-      sd[jj][c] = (c0 + jj < len) ? delta[(size_t)(S.coff + c0 + jj) * kMaxL + c] : 0.0;
+      sd[jj][c] = (c0 + jj < len) ? delta[(size_t)(c0 + jj) * kMaxL + c] : 0.0;
     }
     __syncthreads();
     const int steps = std::min(kCols64, len - c0 + 3) / 4;
@@ -150,18 +149,17 @@ __global__ __launch_bounds__(256) void k_fused_fp64(Layout L, Params P, const fl
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int64_t row = row0 + 16 * t + ln;
-    const int role = row_role(S, row);
+    const bool live = row < L.n;
+    const bool in_i = row >= start && row < start + len;
     float rs = 0.f;
 #pragma unroll
     for (int h = 0; h < NH; ++h)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int c = 16 * h + lg + 4 * q;
-        if (role != 0 && c < l) {
-          const float r = role == 1 ? 0.f
-                          : role == 2 ? R[row * l + c]
-                                      : (float)((double)R[row * l + c] - acc[t][h][q]);
-          if (role != 2) R[row * l + c] = r;
+        if (live && c < l) {
+          const float r = in_i ? 0.f : (float)((double)R[row * l + c] - acc[t][h][q]);
+          R[row * l + c] = r;
           rs = fmaf(r, r, rs);
           csum[h][q] = fmaf(r, r, csum[h][q]);
         }
@@ -169,7 +167,7 @@ __global__ __launch_bounds__(256) void k_fused_fp64(Layout L, Params P, const fl
     if (want_rowsq) {
       rs += __shfl_xor(rs, 16);
       rs += __shfl_xor(rs, 32);
-      if (lg == 0 && row < L.n_pad && (role != 0 || row >= L.n)) rowsq[row] = role != 0 ? rs : 0.f;
+      if (lg == 0 && row < L.n_pad) rowsq[row] = live ? rs : 0.f;
     }
   }
   if (want_colsq) {
@@ -206,7 +204,7 @@ __global__ __launch_bounds__(256) void k_fused_fp64v(Layout L, Params P,
                                                      const float* __restrict__ X,
                                                      const double* __restrict__ delta,
                                                      const Ctl* __restrict__ ctl, int block,
-                                                     Span sp, float* __restrict__ R,
+                                                     float* __restrict__ R,
                                                      float* __restrict__ rowsq,
                                                      float* __restrict__ colsq, int want_rowsq,
                                                      int want_colsq) {
@@ -219,13 +217,12 @@ __global__ __launch_bounds__(256) void k_fused_fp64v(Layout L, Params P,
   const int blk = resolve_block(block, ctl, L.m);
   if (blk < 0) return;
   scaled_exp_table(etab, P.s);  // visible after the first barrier of the chunk loop
-  const Span S = block_span(L, blk, sp);
-  const int64_t start = S.cstart;
-  const int len = S.clen;
+  const int64_t start = (int64_t)blk * L.b;
+  const int len = (int)std::min<int64_t>(L.b, L.n - start);
   const int d = L.d, l = L.l;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int ln = lane % 16, lg = lane / 16;
-  const int64_t row0 = S.rbase + (int64_t)blockIdx.x * kRowsWG + wave * 64;
+  const int64_t row0 = (int64_t)blockIdx.x * kRowsWG + wave * 64;
 
   double xi[4][DV], ni[4];
 #pragma unroll
@@ -241,7 +238,7 @@ __global__ __launch_bounds__(256) void k_fused_fp64v(Layout L, Params P,
     stage_cols64<DV, DP>(X, start, c0, len, d, P, ctl, sx, sn);
     for (int e = threadIdx.x; e < kCols64 * NV; e += 256) {
       const int jj = e / NV, c = e % NV;
-      sd[jj][c] = (c0 + jj < len) ? delta[(size_t)(S.coff + c0 + jj) * kMaxL + c] : 0.0;
+      sd[jj][c] = (c0 + jj < len) ? delta[(size_t)(c0 + jj) * kMaxL + c] : 0.0;
     }
     __syncthreads();
     const int steps = std::min(kCols64, len - c0 + 3) / 4;
@@ -279,7 +276,8 @@ __global__ __launch_bounds__(256) void k_fused_fp64v(Layout L, Params P,
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int64_t row = row0 + 16 * t + ln;
-    const int role = row_role(S, row);
+    const bool live = row < L.n;
+    const bool in_i = row >= start && row < start + len;
     float rs = 0.f;
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
@@ -288,11 +286,9 @@ __global__ __launch_bounds__(256) void k_fused_fp64v(Layout L, Params P,
 #pragma unroll
       for (int cc = 4 * q; cc < 4 * q + 4 && cc < NV; ++cc)
         if (cc == c) v = acc[t][cc];
-      if (role != 0 && c < l) {
-        const float r = role == 1 ? 0.f
-                        : role == 2 ? R[row * l + c]
-                                    : (float)((double)R[row * l + c] - v);
-        if (role != 2) R[row * l + c] = r;
+      if (live && c < l) {
+        const float r = in_i ? 0.f : (float)((double)R[row * l + c] - v);
+        R[row * l + c] = r;
         rs = fmaf(r, r, rs);
         csum[q] = fmaf(r, r, csum[q]);
       }
@@ -300,7 +296,7 @@ __global__ __launch_bounds__(256) void k_fused_fp64v(Layout L, Params P,
     if (want_rowsq) {
       rs += __shfl_xor(rs, 16);
       rs += __shfl_xor(rs, 32);
-      if (lg == 0 && row < L.n_pad && (role != 0 || row >= L.n)) rowsq[row] = role != 0 ? rs : 0.f;
+      if (lg == 0 && row < L.n_pad) rowsq[row] = live ? rs : 0.f;
     }
   }
   if (want_colsq) {
@@ -325,12 +321,11 @@ __global__ __launch_bounds__(256) void k_fused_fp64v(Layout L, Params P,
 
 template <int KERN, int NV>
 hipError_t launch_nv(const Layout& L, const Dev& D, const Params& P, const float* X, int32_t block,
-                     float* R, bool wr, bool wc, hipStream_t st, const Span* sp) {
-  const dim3 g(span_grid(L, sp)), t(256);
-  const Span S = sp ? *sp : Span{};
+                     float* R, bool wr, bool wc, hipStream_t st) {
+  const dim3 g(L.nwg), t(256);
 #define AP_F64V(DV, DP)                                                                          \
   hipLaunchKernelGGL((k_fused_fp64v<KERN, DV, DP, NV>), g, t, 0, st, L, P, X, D.delta, D.ctl,   \
-                     block, S, R, D.rowsq, D.colsq, (int)wr, (int)wc)
+                     block, R, D.rowsq, D.colsq, (int)wr, (int)wc)
   if (L.d == 3) {
     AP_F64V(3, 4);
   } else {
@@ -349,11 +344,10 @@ hipError_t launch_nv(const Layout& L, const Dev& D, const Params& P, const float
 
 template <int KERN, int NH>
 hipError_t launch_nh(const Layout& L, const Dev& D, const Params& P, const float* X, int32_t block,
-                     float* R, bool wr, bool wc, hipStream_t st, const Span* sp) {
-  const dim3 g(span_grid(L, sp)), t(256);
-  const Span S = sp ? *sp : Span{};
+                     float* R, bool wr, bool wc, hipStream_t st) {
+  const dim3 g(L.nwg), t(256);
 #define AP_F64(DV, DP)                                                                           \
-  hipLaunchKernelGGL((k_fused_fp64<KERN, DV, DP, NH>), g, t, 0, st, L, P, X, D.delta, D.ctl, block, S, \
+  hipLaunchKernelGGL((k_fused_fp64<KERN, DV, DP, NH>), g, t, 0, st, L, P, X, D.delta, D.ctl, block, \
                      R, D.rowsq, D.colsq, (int)wr, (int)wc)
   if (L.d == 3) {
     AP_F64(3, 4);
@@ -373,24 +367,24 @@ hipError_t launch_nh(const Layout& L, const Dev& D, const Params& P, const float
 
 template <int KERN>
 hipError_t launch_k(const Layout& L, const Dev& D, const Params& P, const float* X, int32_t block,
-                    float* R, bool wr, bool wc, hipStream_t st, const Span* sp) {
-  if (L.l <= 1) return launch_nv<KERN, 1>(L, D, P, X, block, R, wr, wc, st, sp);
-  if (L.l <= 2) return launch_nv<KERN, 2>(L, D, P, X, block, R, wr, wc, st, sp);
-  if (L.l <= 4) return launch_nv<KERN, 4>(L, D, P, X, block, R, wr, wc, st, sp);
-  if (L.l <= 8) return launch_nv<KERN, 8>(L, D, P, X, block, R, wr, wc, st, sp);
-  if (L.l <= 16) return launch_nh<KERN, 1>(L, D, P, X, block, R, wr, wc, st, sp);
-  return launch_nh<KERN, 2>(L, D, P, X, block, R, wr, wc, st, sp);
+                    float* R, bool wr, bool wc, hipStream_t st) {
+  if (L.l <= 1) return launch_nv<KERN, 1>(L, D, P, X, block, R, wr, wc, st);
+  if (L.l <= 2) return launch_nv<KERN, 2>(L, D, P, X, block, R, wr, wc, st);
+  if (L.l <= 4) return launch_nv<KERN, 4>(L, D, P, X, block, R, wr, wc, st);
+  if (L.l <= 8) return launch_nv<KERN, 8>(L, D, P, X, block, R, wr, wc, st);
+  if (L.l <= 16) return launch_nh<KERN, 1>(L, D, P, X, block, R, wr, wc, st);
+  return launch_nh<KERN, 2>(L, D, P, X, block, R, wr, wc, st);
 }
 
 }  // namespace
 
 hipError_t launch_fused_update64(const Layout& L, const Dev& D, const Params& P, const float* X,
                                  int32_t block, float* R, bool want_rowsq, bool want_colsq,
-                                 hipStream_t st, const Span* sp) {
+                                 hipStream_t st) {
   switch (L.kernel) {
-    case 0: return launch_k<0>(L, D, P, X, block, R, want_rowsq, want_colsq, st, sp);
-    case 1: return launch_k<1>(L, D, P, X, block, R, want_rowsq, want_colsq, st, sp);
-    default: return launch_k<2>(L, D, P, X, block, R, want_rowsq, want_colsq, st, sp);
+    case 0: return launch_k<0>(L, D, P, X, block, R, want_rowsq, want_colsq, st);
+    case 1: return launch_k<1>(L, D, P, X, block, R, want_rowsq, want_colsq, st);
+    default: return launch_k<2>(L, D, P, X, block, R, want_rowsq, want_colsq, st);
   }
 }
 

@@ -687,99 +687,3 @@ def test_epochs_bf16_track_emulated_floor():
         print(f"[bf16] epoch {ep + 1} W err {e:.3e} floor {floor:.3e}", flush=True)
         assert e < 3 * floor, ep
 
-
-LOOK_CASES = [
-    # (seed, n, d, l, b, kernel, noise, ell, look): m not a multiple of look, ragged last block
-    (30, 5000, 3, 7, 512, apo.RBF, 0.05, 0.3, 3),
-    (31, 4500, 5, 32, 256, apo.MATERN52, 0.01, 0.8, 4),
-    (32, 3000, 2, 1, 128, apo.MATERN32, 0.1, 0.2, 8),
-]
-
-
-def _look_case(case):
-    seed, n, d, l, b, kern, noise, ell, look = case
-    w = gen.small(seed, n, d, l, b, kernel=kern, noise=noise, ell=ell)
-    return w, look
-
-
-@pytest.mark.parametrize("case", LOOK_CASES)
-@pytest.mark.parametrize("tile", [ap.TILE_FP64, ap.TILE_FP32, ap.TILE_SPLIT, ap.TILE_BF16])
-def test_lookahead_follows_cyclic_trajectory(case, tile):
-    """Cyclic look-ahead (groups of 3, 4 or 8 blocks): three epochs against the
-    oracle's plain cyclic iterates. FP64 tiles within 1e-5; FP32 and split
-    tiles within twice the FP32-tile floor (or the amplification bound), as
-    without look-ahead; BF16 tiles against a plain BF16 run of the same
-    problem (the grouping changes only the order of the sums), within its
-    own distance from the oracle."""
-    w, look = _look_case(case)
-    s, B, W, R = _gpu(w, tile=tile)
-    s.set_lookahead(look)
-    s.reset(B, W, R)
-    p = to_oracle(w)
-    L = apo.factor(p)
-    if tile == ap.TILE_FP64:
-        tols = [1e-5] * 3
-    elif tile == ap.TILE_BF16:
-        s2, _, W2, R2 = _gpu(w, tile=tile)
-        s2.reset(B, W2, R2)
-    else:
-        floor = fp32_tile_floor(p, 3)
-        base = _epoch_tol(p, L, dense_khat(p))
-        tols = [max(base, 2 * f) * (2 if tile == ap.TILE_SPLIT else 1) for f in floor]
-    Wo, Ro = np.zeros_like(p.B), p.B.copy()
-    for ep in range(3):
-        s.epoch(B, W, R, 1)
-        apo.epoch(p, L, Wo, Ro)
-        e = _rel(W.cpu().numpy(), Wo)
-        if tile == ap.TILE_BF16:
-            s2.epoch(B, W2, R2, 1)
-            e2 = _rel(W2.cpu().numpy(), Wo)
-            print(f"[look {look} tile {tile}] epoch {ep + 1} W err {e:.3e} plain {e2:.3e}",
-                  flush=True)
-            assert e < 2 * e2 + 1e-5, ep
-        else:
-            print(f"[look {look} tile {tile}] epoch {ep + 1} W err {e:.3e} bar {tols[ep]:.3e}",
-                  flush=True)
-            assert e < tols[ep], ep
-        rho, _ = s.rel_residual()
-        rho_o = apo.rel_residual(p, Ro)
-        if tile == ap.TILE_FP64:
-            assert abs(rho - rho_o) <= max(1e-5 * rho_o, 1e-7)
-
-
-def test_lookahead_graph_replay_equals_eager():
-    """Look-ahead epochs replay a captured graph; with profiling on the same
-    launches go out one by one: bitwise the same W and R."""
-    w, look = _look_case(LOOK_CASES[0])
-    sg, B, Wg, Rg = _gpu(w, tile=ap.TILE_FP32)
-    se, _, We, Re = _gpu(w, tile=ap.TILE_FP32)
-    for s_ in (sg, se):
-        s_.set_lookahead(look)
-    se.profile(True)
-    sg.reset(B, Wg, Rg)
-    se.reset(B, We, Re)
-    for ep in range(3):
-        sg.epoch(B, Wg, Rg, 1)
-        se.epoch(B, We, Re, 1)
-        torch.cuda.synchronize()
-        _ = (Wg.sum() + We.sum()).item()
-        assert torch.equal(Wg, We) and torch.equal(Rg, Re), ep
-
-
-def test_lookahead_refuses_what_it_does_not_cover():
-    w, _ = _look_case(LOOK_CASES[0])
-    s, B, W, R = _gpu(w, tile=ap.TILE_FP32)
-    for bad in (0, 9):
-        with pytest.raises(ap.ApError) as e:
-            s.set_lookahead(bad)
-        assert e.value.code == ap.ERR_INVALID_ARG
-    wg = _small(CASES[1], order=apo.GREEDY)
-    sg, _, _, _ = _gpu(wg, tile=ap.TILE_FP32)
-    with pytest.raises(ap.ApError) as e:
-        sg.set_lookahead(2)  # greedy order
-    assert e.value.code == ap.ERR_UNSUPPORTED
-    sb, _, _, _ = _gpu(_small(CASES[0]), tile=ap.TILE_FP32)  # b = 100
-    with pytest.raises(ap.ApError) as e:
-        sb.set_lookahead(2)
-    assert e.value.code == ap.ERR_UNSUPPORTED
-    s.set_lookahead(1)  # always allowed
