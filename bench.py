@@ -719,9 +719,17 @@ def main():
         torch.cuda.empty_cache()
         return res
 
-    def run_compare(wk, Bk, make_k, tile, steps, warmup):
+    oracle_p = {}
+
+    def oracle_for(wk):
+        if wk.name not in oracle_p:
+            oracle_p[wk.name] = p_main if (wk is w and p_main is not None) else oracle_problem(wk)
+        return oracle_p[wk.name]
+
+    def run_compare(wk, Bk, make_k, tile, steps, warmup, key=None):
         """Another tile path: `warmup` + `steps` epochs, timed through the
-        graph, then the FP64 true ratio and its drift from the maintained one."""
+        graph, then the FP64 true ratio and its drift from the maintained one,
+        and (with `key`) the oracle's row-sampled FP64 ratio of the final W."""
         s, t_factor = make_k(tile)
         W, R = s.new_state(Bk)
         s.reset(Bk, W, R)
@@ -752,6 +760,9 @@ def main():
             del Rt
         res["diverged"] = not (math.isfinite(rho) and rho < 1e6 and
                                (res.get("drift") is None or res["drift"] < 1e-2))
+        if key is not None and args.oracle_rows > 0 and math.isfinite(rho):
+            checks.submit(key, oracle_for(wk), W.cpu().numpy(), args.oracle_rows, seed=7,
+                          R_host=R.cpu().numpy().astype(np.float64))
         log(f"[bench] {res['tile']} ({wk.name}): {json.dumps(res)}")
         del s, W, R
         torch.cuda.empty_cache()
@@ -764,7 +775,8 @@ def main():
     for name in ("fp64", "split", "bf16", "fp32"):
         if name != args.main and args.other_steps > 0 and name not in args.skip.split(","):
             log(f"[stage] other path: {name} tiles")
-            paths[name] = run_compare(w, B, make, tiles[name], args.other_steps, 1)
+            paths[name] = run_compare(w, B, make, tiles[name], args.other_steps, 1,
+                                      key=("path", name))
 
     # the same inputs at sigma^2 = 1e-2, where every FP32-grade path holds
     noise2 = None
@@ -776,7 +788,7 @@ def main():
         for name in ("split", "fp32"):
             log(f"[stage] sigma^2 = 1e-2: {name} tiles")
             noise2["paths"][name] = run_compare(w2, B2, lambda t: make_solver(w2, X, t),
-                                                tiles[name], 2, 1)
+                                                tiles[name], 2, 1, key=("noise2", name))
         del B2
 
     upd = main["profiled_epoch"]["fused_update"]
@@ -815,6 +827,11 @@ def main():
         serving = serving_run(checks)
 
     main["oracle_sampled"] = checks.get("main")
+    for name in paths:
+        paths[name]["oracle_sampled"] = checks.get(("path", name))
+    if noise2 is not None:
+        for name in noise2["paths"]:
+            noise2["paths"][name]["oracle_sampled"] = checks.get(("noise2", name))
     if ttt is not None:
         for name in ttt["runs"]:
             ttt["runs"][name]["oracle_sampled"] = checks.get(("ttt", name))
