@@ -269,6 +269,84 @@ def test_limits_fp64_tiles_match_oracle(n, d, l, b, kern, order):
         assert e < 1e-5, ep
 
 
+@pytest.mark.parametrize("tile", [ap.TILE_FP32, ap.TILE_SPLIT])
+@pytest.mark.parametrize("n,d,l,b,kern,order", [
+    (8500, 3, 4, 4096, apo.RBF, apo.GREEDY),     # the largest block, vector-unit product
+    (900, 20, 20, 256, apo.MATERN32, apo.CYCLIC),  # the most features, matrix-core product
+])
+def test_limits_reduced_tiles_match_oracle(n, d, l, b, kern, order, tile):
+    """The size limits on FP32 and split tiles: two epochs against the
+    oracle's iterates, with the bars of the small cases (FP32: twice the
+    emulated FP32-tile floor or the amplification bound; split: twice the
+    amplification bound)."""
+    rng = np.random.default_rng(n + d)
+    w = gen.small(12, n, d, l, b, kernel=kern, noise=0.05,
+                  ell=(0.3 if d == 3 else 2.0) * rng.uniform(0.8, 1.25, size=d), order=order)
+    s, B, W, R = _gpu(w, tile=tile)
+    s.reset(B, W, R)
+    p = to_oracle(w)
+    L = apo.factor(p)
+    K = dense_khat(p)
+    base = _epoch_tol(p, L, K)
+    if tile == ap.TILE_FP32:
+        tol = max(base, 2 * max(fp32_tile_floor(p, 2)))
+    else:
+        tol = 2 * base
+    Wo, Ro = np.zeros_like(p.B), p.B.copy()
+    for ep in range(2):
+        s.epoch(B, W, R, 1)
+        apo.epoch(p, L, Wo, Ro, ep)
+        e = _rel(W.cpu().numpy(), Wo)
+        print(f"[limits] tile {tile} n={n} d={d} b={b} epoch {ep + 1}: W err {e:.3e} "
+              f"bar {tol:.3e}", flush=True)
+        assert e < tol, ep
+
+
+@pytest.mark.parametrize("tile", [ap.TILE_FP32, ap.TILE_SPLIT, ap.TILE_FP64, ap.TILE_BF16])
+def test_single_point_system_is_solved_in_one_update(tile):
+    """n = 1: K^ = s + sigma^2, so one update gives W = B / (s + sigma^2) and
+    R = 0 exactly (the projection zeroes the block's rows), in every tile mode."""
+    w = gen.small(21, 1, 1, 3, 1, kernel=apo.MATERN52, noise=0.25, ell=0.7, outputscale=1.3)
+    s, B, W, R = _gpu(w, tile=tile)
+    s.reset(B, W, R)
+    s.epoch(B, W, R, 1)
+    torch.cuda.synchronize()
+    expect = w.B.astype(np.float64) / (1.3 + 0.25)
+    np.testing.assert_allclose(W.cpu().numpy(), expect, rtol=1e-14, atol=0)
+    assert np.all(R.cpu().numpy() == 0.0)
+    rho, _ = s.rel_residual()
+    assert rho == 0.0
+
+
+@pytest.mark.parametrize("tile", [ap.TILE_FP32, ap.TILE_SPLIT, ap.TILE_FP64])
+@pytest.mark.parametrize("n,d,l,b", [
+    (2, 1, 3, 1),      # two unit blocks
+    (300, 1, 9, 100),  # one feature; l = 9 takes the FP32 matrix-core product
+    (65, 20, 32, 64),  # the widest features with l = 32, a last block of one point
+])
+def test_degenerate_shapes_match_oracle(n, d, l, b, tile):
+    w = gen.small(22, n, d, l, b, kernel=apo.RBF, noise=0.1, ell=0.6 if d == 1 else 3.0)
+    s, B, W, R = _gpu(w, tile=tile)
+    s.reset(B, W, R)
+    p = to_oracle(w)
+    L = apo.factor(p)
+    K = dense_khat(p)
+    tol = 1e-5 if tile == ap.TILE_FP64 else max(_epoch_tol(p, L, K),
+                                                 2 * max(fp32_tile_floor(p, 3)))
+    if tile == ap.TILE_SPLIT:
+        tol *= 2
+    Wo, Ro = np.zeros_like(p.B), p.B.copy()
+    for ep in range(3):
+        s.epoch(B, W, R, 1)
+        apo.epoch(p, L, Wo, Ro)
+        e = _rel(W.cpu().numpy(), Wo)
+        print(f"[shape] tile {tile} n={n} d={d} l={l} b={b} epoch {ep + 1}: W err {e:.3e} "
+              f"bar {tol:.3e}", flush=True)
+        assert e < tol, ep
+        rho, _ = s.rel_residual()
+        assert abs(rho - apo.rel_residual(p, Ro)) <= max(tol * apo.rel_residual(p, Ro), 1e-7)
+
+
 def test_random_order_single_block_equals_cyclic():
     """m = 1: every draw is block 0, so random order is cyclic order bit for bit."""
     case = CASES[4]  # b = n
