@@ -64,16 +64,43 @@ MEASURED_TRAFFIC = {
         "sha256": "47fe79259ca7e8cc5f9fe3103236d1312c114a5a3f151562d6e887b48d5fe4ea",
     },
     ("fp32", "c3"): {
-        "bytes": 157440.0 * 1024 * 2.0 + 250001.0 * 1024 * 1.0,
+        "bytes": 157449.0 * 1024 * 2.0 + 250001.0 * 1024 * 1.0,
         "files": ("update.hip", "ap_internal.h"),
-        "sha256": "495d17763a16bffedf075fbebdf2ac40d75fa053061163c15fe55c17259bfcac",
+        "sha256": "c8b789328ae986719541f6572645e47eb81d6b195678b668ef0fd4f9bbb1a449",
+    },
+    ("fp32", "c2"): {
+        "bytes": 17178.0 * 1024 * 2.0 + 16385.0 * 1024 * 1.0,
+        "files": ("update.hip", "ap_internal.h"),
+        "sha256": "c8b789328ae986719541f6572645e47eb81d6b195678b668ef0fd4f9bbb1a449",
     },
     ("split", "c3"): {
         "bytes": 157975.0 * 1024 * 2.0 + 250001.0 * 1024 * 1.0,
         "files": ("update.hip", "ap_internal.h"),
-        "sha256": "495d17763a16bffedf075fbebdf2ac40d75fa053061163c15fe55c17259bfcac",
+        "sha256": "c8b789328ae986719541f6572645e47eb81d6b195678b668ef0fd4f9bbb1a449",
     },
 }
+
+
+def fused_kernel(tile: int, d: int, l: int):
+    """The fused-update kernel a launch of this tile mode and shape runs, and
+    the matrix-core flops it issues per kernel entry (0 where the product with
+    the step runs on the vector units)."""
+    from paper_2310_17137_amd import ap
+    dp = (d + 3) // 4 * 4
+    if tile == ap.TILE_FP32:
+        if l <= 8:
+            return "k_fused_fp32v", 0
+        if l <= 16 and dp <= 12:
+            return "k_fused_fp32h", 2 * 16          # 16x16x4: 16 right-hand sides
+        return "k_fused_fp32", 2 * 32               # 32x32x2: 32 right-hand sides
+    if tile == ap.TILE_FP64:
+        if l <= 8:
+            return "k_fused_fp64v", 0
+        return "k_fused_fp64", 2 * 16 * (1 if l <= 16 else 2)
+    if tile == ap.TILE_SPLIT:
+        return "k_fused_split", 6 * 2 * 32          # six BF16 products, 32 right-hand sides
+    ks = (3 * d + 6 + 15) // 16                     # BF16: x.x' on 16 KS slots, then the product
+    return "k_fused_bf16", 2 * 16 * ks + 2 * 32
 
 
 def measured_traffic(tile: str, workload_name: str):
@@ -798,17 +825,18 @@ def main():
     achieved = flops_launch / avg / 1e12
     peak = {ap.TILE_FP32: PEAK_FP32_TFLOPS, ap.TILE_FP64: PEAK_FP64_TFLOPS}.get(
         main_tile, PEAK_BF16_TFLOPS)
-    mfma_flops_launch = flops_launch * (6 if main_tile == ap.TILE_SPLIT else 1)
+    kname, mfma_per_entry = fused_kernel(main_tile, w.d, w.l)
+    mfma_flops_launch = mfma_per_entry * entries_per_launch
     # R read and written (FP32) plus the row features: the FP64 prepared
     # copies (stride d rounded up to 4) on FP32 and split tiles, X itself on
     # FP64 tiles
     feat = w.n * (w.d * 4 if main_tile == ap.TILE_FP64 else ((w.d + 3) // 4 * 4) * 8)
     bytes_launch = 2.0 * w.n * w.l * 4 + feat
-    roofline = {"bound": "mfma", "achieved": achieved, "peak": peak,
+    roofline = {"bound": "mfma" if mfma_per_entry else "alu", "achieved": achieved, "peak": peak,
                 "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": measured_traffic(main["tile"], w.name),
                 "algorithmic_bytes_per_launch": bytes_launch,
-                "kernel": f"k_fused_{main['tile']} (fused K-tile residual update)",
+                "kernel": f"{kname} (fused K-tile residual update)",
                 "flops_counted": "2 (d + l) per kernel entry: x.x' and the product with the step",
                 "avg_launch_us": avg * 1e6,
                 "flops_per_entry": 2 * (w.d + w.l), "entries_per_launch": entries_per_launch,

@@ -24,6 +24,7 @@ namespace {
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
 typedef __attribute__((ext_vector_type(2))) float f32x2;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
 typedef __attribute__((ext_vector_type(16))) float f32x16;
 typedef __attribute__((ext_vector_type(16))) double f64x16;
 
@@ -311,7 +312,7 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const double* __re
     for (int t = 0; t < 2; ++t)
 #pragma unroll
       for (int v = 0; v < 16; ++v) part[t][v] = 0.f;
-#pragma unroll 2
+#pragma unroll
     for (int st = 0; st < 16; ++st) {
       const int cc = 2 * st + g;  // this lane's chunk column
       double xc[DV];
@@ -331,6 +332,124 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const double* __re
       for (int v = 0; v < 16; ++v) acc[t][v] += (double)part[t][v];
   }
   epilogue(L, row0, start, len, acc, R, rowsq, colsq, want_rowsq, want_colsq, (int)blockIdx.x);
+}
+
+// FP32 tiles with 8 < l <= 16: the product on v_mfma_f32_16x16x4f32, whose 16
+// right-hand sides cover l where the 32-row tile of k_fused_fp32 would leave half
+// its multiply-adds idle (and the FP32 matrix instructions do not overlap the
+// vector work of the kernel map, so idle matrix cycles are lost cycles). A wave
+// owns four 16-row tiles; per step of 4 chunk columns a lane evaluates one
+// kernel value per row tile (row lane % 16, column lane / 16), the same kernel
+// values per lane as the 32-row kernel, and the matrix cores accumulate
+// part[r][i] += delta^T[r][j] K^T[j][i]. FP32 sums per chunk, FP64 across chunks.
+template <int KERN, int DV, int DP>
+__global__ __launch_bounds__(256) void k_fused_fp32h(Layout L, const double* __restrict__ xv,
+                                                     const float* __restrict__ dtile,
+                                                     const Ctl* __restrict__ ctl, int block,
+                                                     float* __restrict__ R,
+                                                     float* __restrict__ rowsq,
+                                                     float* __restrict__ colsq, int want_rowsq,
+                                                     int want_colsq) {
+  constexpr int NH = 16;  // right-hand sides of the tile
+  __shared__ double sx[kChunk][DP];
+  __shared__ double sn[kChunk];
+  __shared__ float sd[kChunk][NH];
+  __shared__ float red[4][NH];
+  const int blk = resolve_block(block, ctl, L.m);
+  if (blk < 0) return;
+  const int64_t start = (int64_t)blk * L.b;
+  const int len = (int)std::min<int64_t>(L.b, L.n - start);
+  const int nch = (len + kChunk - 1) / kChunk;
+  const int l = L.l;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int ln = lane % 16, lg = lane / 16;
+  const int64_t row0 = (int64_t)blockIdx.x * kRowsWG + wave * 64;
+
+  double xr[4][DV], nr[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+#pragma unroll
+    for (int k = 0; k < DV; ++k) xr[t][k] = xv[(row0 + 16 * t + ln) * DP + k];
+    nr[t] = norm2<DV>(xr[t]);
+  }
+  double acc[4][4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[t][q] = 0.0;
+
+  for (int ch = 0; ch < nch; ++ch) {
+    const int64_t cb = start + (int64_t)ch * kChunk;
+    __syncthreads();
+    stage_cols<DV, DP>(xv, cb, &sx[0][0], sn);
+    for (int e = threadIdx.x; e < kChunk * NH; e += 256)
+      sd[e / NH][e % NH] = dtile[((int64_t)ch * kChunk + e / NH) * kMaxL + e % NH];
+    __syncthreads();
+    f32x4 part[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) part[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int st = 0; st < kChunk / 4; ++st) {
+      const int jj = 4 * st + lg;  // this lane's chunk column
+      double xc[DV];
+#pragma unroll
+      for (int k = 0; k < DV; ++k) xc[k] = sx[jj][k];
+      const double nc = sn[jj];
+      const float dv = sd[jj][ln];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const float kv = kmap_acc<KERN>(dist2n<DV>(xr[t], nr[t], xc, nc));
+        part[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(dv, kv, part[t], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[t][q] += (double)part[t][q];
+  }
+
+  // lane holds acc[t][q]: row row0 + 16 t + lane % 16, right-hand side c = 4 (lane / 16) + q
+  float csum[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int64_t row = row0 + 16 * t + ln;
+    const bool live = row < L.n;
+    const bool in_i = row >= start && row < start + len;
+    float rs = 0.f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = 4 * lg + q;
+      if (live && c < l) {
+        const float r = in_i ? 0.f : (float)((double)R[row * l + c] - acc[t][q]);
+        R[row * l + c] = r;
+        rs = fmaf(r, r, rs);
+        csum[q] = fmaf(r, r, csum[q]);
+      }
+    }
+    if (want_rowsq) {
+      rs += __shfl_xor(rs, 16);
+      rs += __shfl_xor(rs, 32);
+      if (lg == 0 && row < L.n_pad) rowsq[row] = live ? rs : 0.f;
+    }
+  }
+  if (want_colsq) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      float x = csum[q];
+      x += __shfl_xor(x, 1);
+      x += __shfl_xor(x, 2);
+      x += __shfl_xor(x, 4);
+      x += __shfl_xor(x, 8);
+      if (ln == 0) red[wave][4 * lg + q] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < kMaxL) {
+      const int c = threadIdx.x;
+      float v = 0.f;
+      if (c < NH) v = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+      colsq[(size_t)blockIdx.x * kMaxL + c] = c < l ? v : 0.f;
+    }
+  }
 }
 
 // FP32 tiles with few right-hand sides (l <= 8): the product with the step on
@@ -615,9 +734,16 @@ hipError_t launch_fp32(const Layout& L, const Dev& D, int32_t block, float* R, b
   if (L.l <= 8) return launch_fp32v<KERN, 8>(L, D, block, R, wr, wc, st);
   const dim3 g(L.nwg), t(256);
   const float* dt = (const float*)D.dtile;
-#define AP_FP32(DV, DP)                                                                        \
-  hipLaunchKernelGGL((k_fused_fp32<KERN, DV, DP>), g, t, 0, st, L, D.xv, dt, D.ctl, block, R, \
-                     D.rowsq, D.colsq, (int)wr, (int)wc)
+  // the 16-row tile holds four rows' features per lane; past 12 features that
+  // costs the occupancy the matrix saving buys back
+  const bool half = L.l <= 16 && L.dp <= 12;
+#define AP_FP32(DV, DP)                                                                          \
+  if (half)                                                                                      \
+    hipLaunchKernelGGL((k_fused_fp32h<KERN, DV, DP>), g, t, 0, st, L, D.xv, dt, D.ctl, block, R, \
+                       D.rowsq, D.colsq, (int)wr, (int)wc);                                      \
+  else                                                                                           \
+    hipLaunchKernelGGL((k_fused_fp32<KERN, DV, DP>), g, t, 0, st, L, D.xv, dt, D.ctl, block, R,  \
+                       D.rowsq, D.colsq, (int)wr, (int)wc)
   if (L.d == 3) {
     AP_FP32(3, 4);
   } else {

@@ -272,7 +272,8 @@ def test_limits_fp64_tiles_match_oracle(n, d, l, b, kern, order):
 @pytest.mark.parametrize("tile", [ap.TILE_FP32, ap.TILE_SPLIT])
 @pytest.mark.parametrize("n,d,l,b,kern,order", [
     (8500, 3, 4, 4096, apo.RBF, apo.GREEDY),     # the largest block, vector-unit product
-    (900, 20, 20, 256, apo.MATERN32, apo.CYCLIC),  # the most features, matrix-core product
+    (900, 20, 20, 256, apo.MATERN32, apo.CYCLIC),  # the most features, 32-row matrix tile
+    (900, 12, 12, 256, apo.MATERN52, apo.CYCLIC),  # the most features of the 16-row matrix tile
 ])
 def test_limits_reduced_tiles_match_oracle(n, d, l, b, kern, order, tile):
     """The size limits on FP32 and split tiles: two epochs against the
@@ -321,7 +322,7 @@ def test_single_point_system_is_solved_in_one_update(tile):
 @pytest.mark.parametrize("tile", [ap.TILE_FP32, ap.TILE_SPLIT, ap.TILE_FP64])
 @pytest.mark.parametrize("n,d,l,b", [
     (2, 1, 3, 1),      # two unit blocks
-    (300, 1, 9, 100),  # one feature; l = 9 takes the FP32 matrix-core product
+    (300, 1, 9, 100),  # one feature; l = 9 takes the FP32 16-row matrix tile
     (65, 20, 32, 64),  # the widest features with l = 32, a last block of one point
 ])
 def test_degenerate_shapes_match_oracle(n, d, l, b, tile):
