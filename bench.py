@@ -45,9 +45,6 @@ sys.path.insert(0, ROOT)
 PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 MFMA
 PEAK_FP32_TFLOPS = 157.3       # MI355X dense FP32 matrix
 PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 (vector and matrix)
-PEAK_HBM_GBS = 8000.0
-# transcendental issue: 256 CUs x 32 lanes/cycle (half rate) x 2.4 GHz
-PEAK_TRANS_PER_S = 256 * 32 * 2.4e9
 
 
 TILE_NAMES = {0: "fp32", 1: "bf16", 2: "split", 3: "fp64"}
