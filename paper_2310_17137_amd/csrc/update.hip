@@ -338,23 +338,25 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const double* __re
 // right-hand sides cover l where the 32-row tile of k_fused_fp32 would leave half
 // its multiply-adds idle (and the FP32 matrix instructions do not overlap the
 // vector work of the kernel map, so idle matrix cycles are lost cycles). A wave
-// owns four 16-row tiles; per step of 4 chunk columns a lane evaluates one
-// kernel value per row tile (row lane % 16, column lane / 16), the same kernel
-// values per lane as the 32-row kernel, and the matrix cores accumulate
+// owns RT 16-row tiles (the workgroup's 256 rows over 256 / (16 RT) waves); per
+// step of 4 chunk columns a lane evaluates one kernel value per row tile (row
+// lane % 16, column lane / 16) and the matrix cores accumulate
 // part[r][i] += delta^T[r][j] K^T[j][i]. FP32 sums per chunk, FP64 across chunks.
-template <int KERN, int DV, int DP>
-__global__ __launch_bounds__(256) void k_fused_fp32h(Layout L, const double* __restrict__ xv,
+template <int KERN, int DV, int DP, int RT>
+__global__ __launch_bounds__(kRowsWG / (16 * RT) * 64) void k_fused_fp32h(Layout L, const double* __restrict__ xv,
                                                      const float* __restrict__ dtile,
                                                      const Ctl* __restrict__ ctl, int block,
                                                      float* __restrict__ R,
                                                      float* __restrict__ rowsq,
                                                      float* __restrict__ colsq, int want_rowsq,
                                                      int want_colsq) {
-  constexpr int NH = 16;  // right-hand sides of the tile
+  constexpr int NH = 16;                     // right-hand sides of the tile
+  constexpr int NW = kRowsWG / (16 * RT);    // waves of the workgroup
+  constexpr int NT = 64 * NW;                // its threads
   __shared__ double sx[kChunk][DP];
   __shared__ double sn[kChunk];
   __shared__ float sd[kChunk][NH];
-  __shared__ float red[4][NH];
+  __shared__ float red[NW][NH];
   const int blk = resolve_block(block, ctl, L.m);
   if (blk < 0) return;
   const int64_t start = (int64_t)blk * L.b;
@@ -363,18 +365,18 @@ __global__ __launch_bounds__(256) void k_fused_fp32h(Layout L, const double* __r
   const int l = L.l;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int ln = lane % 16, lg = lane / 16;
-  const int64_t row0 = (int64_t)blockIdx.x * kRowsWG + wave * 64;
+  const int64_t row0 = (int64_t)blockIdx.x * kRowsWG + wave * 16 * RT;
 
-  double xr[4][DV], nr[4];
+  double xr[RT][DV], nr[RT];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < RT; ++t) {
 #pragma unroll
     for (int k = 0; k < DV; ++k) xr[t][k] = xv[(row0 + 16 * t + ln) * DP + k];
     nr[t] = norm2<DV>(xr[t]);
   }
-  double acc[4][4];
+  double acc[RT][4];
 #pragma unroll
-  for (int t = 0; t < 4; ++t)
+  for (int t = 0; t < RT; ++t)
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[t][q] = 0.0;
 
@@ -382,12 +384,12 @@ __global__ __launch_bounds__(256) void k_fused_fp32h(Layout L, const double* __r
     const int64_t cb = start + (int64_t)ch * kChunk;
     __syncthreads();
     stage_cols<DV, DP>(xv, cb, &sx[0][0], sn);
-    for (int e = threadIdx.x; e < kChunk * NH; e += 256)
+    for (int e = threadIdx.x; e < kChunk * NH; e += NT)
       sd[e / NH][e % NH] = dtile[((int64_t)ch * kChunk + e / NH) * kMaxL + e % NH];
     __syncthreads();
-    f32x4 part[4];
+    f32x4 part[RT];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) part[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < RT; ++t) part[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int st = 0; st < kChunk / 4; ++st) {
       const int jj = 4 * st + lg;  // this lane's chunk column
@@ -397,13 +399,13 @@ __global__ __launch_bounds__(256) void k_fused_fp32h(Layout L, const double* __r
       const double nc = sn[jj];
       const float dv = sd[jj][ln];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
+      for (int t = 0; t < RT; ++t) {
         const float kv = kmap_acc<KERN>(dist2n<DV>(xr[t], nr[t], xc, nc));
         part[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(dv, kv, part[t], 0, 0, 0);
       }
     }
 #pragma unroll
-    for (int t = 0; t < 4; ++t)
+    for (int t = 0; t < RT; ++t)
 #pragma unroll
       for (int q = 0; q < 4; ++q) acc[t][q] += (double)part[t][q];
   }
@@ -411,7 +413,7 @@ __global__ __launch_bounds__(256) void k_fused_fp32h(Layout L, const double* __r
   // lane holds acc[t][q]: row row0 + 16 t + lane % 16, right-hand side c = 4 (lane / 16) + q
   float csum[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
+  for (int t = 0; t < RT; ++t) {
     const int64_t row = row0 + 16 * t + ln;
     const bool live = row < L.n;
     const bool in_i = row >= start && row < start + len;
@@ -446,7 +448,10 @@ __global__ __launch_bounds__(256) void k_fused_fp32h(Layout L, const double* __r
     if (threadIdx.x < kMaxL) {
       const int c = threadIdx.x;
       float v = 0.f;
-      if (c < NH) v = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+      if (c < NH) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) v += red[w][c];
+      }
       colsq[(size_t)blockIdx.x * kMaxL + c] = c < l ? v : 0.f;
     }
   }
@@ -725,6 +730,12 @@ hipError_t launch_fp32v(const Layout& L, const Dev& D, int32_t block, float* R, 
   return hipGetLastError();
 }
 
+// Row tiles per wave of the 16-row kernel: the workgroup's 256 rows go to
+// 256 / (16 kTilesH) waves. Two tiles (eight waves) keep the row features of a
+// lane within the register budget of four waves per SIMD; four tiles held two.
+constexpr int kTilesH = 2;
+constexpr int kThreadsH = kRowsWG / (16 * kTilesH) * 64;
+
 template <int KERN>
 hipError_t launch_fp32(const Layout& L, const Dev& D, int32_t block, float* R, bool wr, bool wc,
                        hipStream_t st) {
@@ -734,13 +745,11 @@ hipError_t launch_fp32(const Layout& L, const Dev& D, int32_t block, float* R, b
   if (L.l <= 8) return launch_fp32v<KERN, 8>(L, D, block, R, wr, wc, st);
   const dim3 g(L.nwg), t(256);
   const float* dt = (const float*)D.dtile;
-  // the 16-row tile holds four rows' features per lane; past 12 features that
-  // costs the occupancy the matrix saving buys back
-  const bool half = L.l <= 16 && L.dp <= 12;
+  const bool half = L.l <= 16;
 #define AP_FP32(DV, DP)                                                                          \
   if (half)                                                                                      \
-    hipLaunchKernelGGL((k_fused_fp32h<KERN, DV, DP>), g, t, 0, st, L, D.xv, dt, D.ctl, block, R, \
-                       D.rowsq, D.colsq, (int)wr, (int)wc);                                      \
+    hipLaunchKernelGGL((k_fused_fp32h<KERN, DV, DP, kTilesH>), g, dim3(kThreadsH), 0, st, L,     \
+                       D.xv, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc);           \
   else                                                                                           \
     hipLaunchKernelGGL((k_fused_fp32<KERN, DV, DP>), g, t, 0, st, L, D.xv, dt, D.ctl, block, R,  \
                        D.rowsq, D.colsq, (int)wr, (int)wc)

@@ -88,14 +88,13 @@ def _chunk_products(Kt, dt, group: int) -> np.ndarray:
     return out
 
 
-def fp32_product_group(d: int, l: int) -> int:
+def fp32_product_group(l: int) -> int:
     """Products the FP32 tiles add per rounding of a chunk's FP32 accumulator:
-    one (vector FMAs, l <= 8), four (v_mfma_f32_16x16x4f32, 8 < l <= 16 with
-    at most 12 features, the features padded to a multiple of 4) or two
-    (v_mfma_f32_32x32x2f32)."""
+    one (vector FMAs, l <= 8), four (v_mfma_f32_16x16x4f32, 8 < l <= 16) or
+    two (v_mfma_f32_32x32x2f32)."""
     if l <= 8:
         return 1
-    if l <= 16 and (d + 3) // 4 * 4 <= 12:
+    if l <= 16:
         return 4
     return 2
 
@@ -108,7 +107,7 @@ def tile_trajectory(p, epochs: int, mode: str = "fp32", log=None):
 
     mode "fp32": every kernel value K^_ij rounded once to FP32 and the step
     s delta rounded to FP32; each 32-column chunk summed on an FP32
-    accumulator as the FP32 tile kernel for this l and d forms it
+    accumulator as the FP32 tile kernel for this l forms it
     (fp32_product_group). mode "bf16":
     the kernel values over s and the step s delta rounded to BF16, sixteen
     products per accumulator step (v_mfma_f32_32x32x16_bf16). In both the
@@ -117,7 +116,7 @@ def tile_trajectory(p, epochs: int, mode: str = "fp32", log=None):
     of each block are formed as needed, so large n fits."""
     from oracle import apo
     L = apo.factor(p)
-    group = fp32_product_group(p.X.shape[1], p.B.shape[1])
+    group = fp32_product_group(p.B.shape[1])
     Wo, Ro = np.zeros_like(p.B), p.B.copy()
     W, R = np.zeros_like(p.B), p.B.astype(np.float32).astype(np.float64)
     so = p.outputscale

@@ -273,7 +273,9 @@ def test_limits_fp64_tiles_match_oracle(n, d, l, b, kern, order):
 @pytest.mark.parametrize("n,d,l,b,kern,order", [
     (8500, 3, 4, 4096, apo.RBF, apo.GREEDY),     # the largest block, vector-unit product
     (900, 20, 20, 256, apo.MATERN32, apo.CYCLIC),  # the most features, 32-row matrix tile
-    (900, 12, 12, 256, apo.MATERN52, apo.CYCLIC),  # the most features of the 16-row matrix tile
+    (900, 20, 12, 256, apo.MATERN52, apo.CYCLIC),  # the most features, 16-row matrix tile
+    (700, 11, 16, 128, apo.RBF, apo.GREEDY),     # 11 features padded to 12, 16-row tile
+    (600, 16, 10, 100, apo.MATERN32, apo.CYCLIC),  # 16 features, 16-row tile, ragged blocks
 ])
 def test_limits_reduced_tiles_match_oracle(n, d, l, b, kern, order, tile):
     """The size limits on FP32 and split tiles: two epochs against the
