@@ -15,6 +15,7 @@
 // columns) the second product's B operand, so the kernel values go from the
 // map straight into the next MFMA without leaving registers.
 #include <algorithm>
+#include <type_traits>
 
 #include "ap_internal.h"
 
@@ -144,14 +145,15 @@ __device__ __forceinline__ bf16x8 pack8(const f32x16& v, int base) {
   return r;
 }
 
-// Epilogue shared by both tile precisions. acc[t][v] holds, for data row
-// row0 + 32 t + lane % 32, the update of column m = 8 (v / 4) + 4 (lane / 32) + v % 4.
-template <typename Acc>
+// Epilogue of the 32-row tile kernels (RT row tiles per wave, NW waves).
+// acc[t][v] holds, for data row row0 + 32 t + lane % 32, the update of column
+// m = 8 (v / 4) + 4 (lane / 32) + v % 4.
+template <int RT, int NW, typename Acc>
 __device__ __forceinline__ void epilogue(const Layout& L, int64_t row0, int64_t start, int len,
-                                         const Acc acc[2], float* __restrict__ R,
+                                         const Acc acc[RT], float* __restrict__ R,
                                          float* __restrict__ rowsq, float* __restrict__ colsq,
                                          bool want_rowsq, bool want_colsq, int wg) {
-  __shared__ float red[4][kMaxL];
+  __shared__ float red[NW][kMaxL];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int nl = lane % 32, g = lane / 32;
   const int l = L.l;
@@ -159,7 +161,7 @@ __device__ __forceinline__ void epilogue(const Layout& L, int64_t row0, int64_t 
 #pragma unroll
   for (int v = 0; v < 16; ++v) csum[v] = 0.f;
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < RT; ++t) {
     const int64_t row = row0 + 32 * t + nl;
     const bool in_i = row >= start && row < start + len;
     const bool live = row < L.n;
@@ -197,7 +199,9 @@ __device__ __forceinline__ void epilogue(const Layout& L, int64_t row0, int64_t 
     __syncthreads();
     if (threadIdx.x < kMaxL) {
       const int m = threadIdx.x;
-      float s = ((red[0][m] + red[1][m]) + red[2][m]) + red[3][m];
+      float s = 0.f;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) s += red[w][m];
       colsq[(size_t)wg * kMaxL + m] = m < l ? s : 0.f;
     }
   }
@@ -257,24 +261,52 @@ __global__ __launch_bounds__(256) void k_fused_bf16(Layout L, const uint16_t* __
       acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(d1, pack8(s, 8), acc[t], 0, 0, 0);
     }
   }
-  epilogue(L, row0, start, len, acc, R, rowsq, colsq, want_rowsq, want_colsq, (int)blockIdx.x);
+  epilogue<2, 4>(L, row0, start, len, acc, R, rowsq, colsq, want_rowsq, want_colsq, (int)blockIdx.x);
+}
+
+// Asynchronous staging of one chunk (block columns cb .. cb + 31) for the FP32
+// tile kernels: the columns' prepared features v_j (kChunk x DP doubles), their
+// norms |v_j|^2 and the first NS columns of the step's rows (kChunk x NS
+// floats) are copied from global memory straight into LDS with global_load_lds
+// (each lane moves 16 or 4 bytes to base + lane * size; no registers are
+// held). A wave-load moves 1 KiB; the waves take them in turn. The caller
+// waits for the copies (s_waitcnt) and crosses a barrier before reading.
+template <int DP, int NS, int NW>
+__device__ __forceinline__ void stage_async(const double* __restrict__ xv,
+                                            const double* __restrict__ xn,
+                                            const float* __restrict__ dtile, int64_t start,
+                                            int ch, double* sx, double* sn, float* sd) {
+  constexpr int QR = NS / 4;  // lanes per step row
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int64_t cb = start + (int64_t)ch * kChunk;
+  const float* d0 = dtile + (int64_t)ch * kChunk * kMaxL;
+  for (int q = wave; q < kChunk * NS / 256; q += NW) {
+    const int row = (64 / QR) * q + lane / QR;
+    __builtin_amdgcn_global_load_lds(d0 + row * kMaxL + 4 * (lane % QR), sd + 256 * q, 16, 0, 0);
+  }
+  for (int q = wave; q < kChunk * DP / 128; q += NW)
+    __builtin_amdgcn_global_load_lds(xv + cb * DP + 128 * q + 2 * lane, sx + 128 * q, 16, 0, 0);
+  if (wave == NW - 1)  // 32 norms as 64 dwords: 4-byte copies keep odd cb aligned
+    __builtin_amdgcn_global_load_lds((const uint32_t*)(xn + cb) + lane, sn, 4, 0, 0);
 }
 
 // FP32 tiles: the prepared features in FP64, the squared distance in FP64, the
 // kernel map in FP32 (kmap_acc, within about 2 ulp), and the product with the
 // step on v_mfma_f32_32x32x2f32 (one kernel value per lane per step). Each
-// chunk's column features and step are staged in LDS.
-template <int KERN, int DV, int DP>
-__global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const double* __restrict__ xv,
-                                                    const float* __restrict__ dtile,
-                                                    const Ctl* __restrict__ ctl, int block,
-                                                    float* __restrict__ R,
-                                                    float* __restrict__ rowsq,
-                                                    float* __restrict__ colsq, int want_rowsq,
-                                                    int want_colsq) {
-  __shared__ double sx[kChunk][DP];
-  __shared__ double sn[kChunk];
-  __shared__ float sd[kChunk][kMaxL];
+// chunk's column features, norms and step rows are staged in LDS, double-
+// buffered: chunk c + 1 is copied into one buffer while chunk c is computed
+// from the other, with one barrier per chunk. The rows are held as -2 v_i and
+// the columns as v_j: the products equal v_i . (-2 v_j) exactly.
+template <int KERN, int DV, int DP, int RT>
+__global__ __launch_bounds__(kRowsWG / (32 * RT) * 64) void k_fused_fp32(
+    Layout L, const double* __restrict__ xv, const double* __restrict__ xn,
+    const float* __restrict__ dtile, const Ctl* __restrict__ ctl, int block,
+    float* __restrict__ R, float* __restrict__ rowsq, float* __restrict__ colsq, int want_rowsq,
+    int want_colsq) {
+  constexpr int NW = kRowsWG / (32 * RT);  // waves of the workgroup
+  __shared__ __attribute__((aligned(16))) double sx[2][kChunk][DP];
+  __shared__ __attribute__((aligned(16))) double sn[2][kChunk];
+  __shared__ __attribute__((aligned(16))) float sd[2][kChunk][kMaxL];
   const int blk = resolve_block(block, ctl, L.m);
   if (blk < 0) return;
   const int64_t start = (int64_t)blk * L.b;
@@ -282,34 +314,38 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const double* __re
   const int nch = (len + kChunk - 1) / kChunk;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int nl = lane % 32, g = lane / 32;
-  const int64_t row0 = (int64_t)blockIdx.x * kRowsWG + wave * 64;
+  const int64_t row0 = (int64_t)blockIdx.x * kRowsWG + wave * 32 * RT;
 
-  double xr[2][DV], nr[2];
+  stage_async<DP, kMaxL, NW>(xv, xn, dtile, start, 0, &sx[0][0][0], sn[0], &sd[0][0][0]);
+  double xr[RT][DV], nr[RT];  // -2 v_i and |v_i|^2
 #pragma unroll
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < RT; ++t) {
 #pragma unroll
-    for (int k = 0; k < DV; ++k) xr[t][k] = xv[(row0 + 32 * t + nl) * DP + k];
-    nr[t] = norm2<DV>(xr[t]);
+    for (int k = 0; k < DV; ++k) xr[t][k] = -2.0 * xv[(row0 + 32 * t + nl) * DP + k];
+    nr[t] = xn[row0 + 32 * t + nl];
   }
   // Each chunk's 32 products accumulate in FP32 on the matrix cores; the chunk
   // sums then accumulate in FP64, so the rounding of the long sum over the
   // block stays at the level of one chunk.
-  f64x16 acc[2];
+  f64x16 acc[RT];
 #pragma unroll
-  for (int t = 0; t < 2; ++t)
+  for (int t = 0; t < RT; ++t)
 #pragma unroll
     for (int v = 0; v < 16; ++v) acc[t][v] = 0.0;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
 
-  for (int ch = 0; ch < nch; ++ch) {
-    const int64_t cb = start + (int64_t)ch * kChunk;
-    __syncthreads();
-    stage_cols<DV, DP>(xv, cb, &sx[0][0], sn);
-    for (int e = threadIdx.x; e < kChunk * kMaxL; e += 256)
-      (&sd[0][0])[e] = dtile[(int64_t)ch * kChunk * kMaxL + e];
-    __syncthreads();
-    f32x16 part[2];
+  // One chunk from buffer B (a compile-time constant, so that the LDS reads
+  // keep immediate offsets), the next chunk's copies going into the other.
+  auto chunk = [&](auto buf, int ch) {
+    constexpr int B = decltype(buf)::value;
+    // the other buffer was last read before the previous barrier
+    if (ch + 1 < nch)
+      stage_async<DP, kMaxL, NW>(xv, xn, dtile, start, ch + 1, &sx[B ^ 1][0][0], sn[B ^ 1],
+                                 &sd[B ^ 1][0][0]);
+    f32x16 part[RT];
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < RT; ++t)
 #pragma unroll
       for (int v = 0; v < 16; ++v) part[t][v] = 0.f;
 #pragma unroll
@@ -317,21 +353,28 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const double* __re
       const int cc = 2 * st + g;  // this lane's chunk column
       double xc[DV];
 #pragma unroll
-      for (int k = 0; k < DV; ++k) xc[k] = sx[cc][k];
-      const double nc = sn[cc];
-      const float dv = sd[cc][nl];
+      for (int k = 0; k < DV; ++k) xc[k] = sx[B][cc][k];
+      const double nc = sn[B][cc];
+      const float dv = sd[B][cc][nl];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
+      for (int t = 0; t < RT; ++t) {
         const float kv = kmap_acc<KERN>(dist2n<DV>(xr[t], nr[t], xc, nc));
         part[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(dv, kv, part[t], 0, 0, 0);
       }
     }
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < RT; ++t)
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[t][v] += (double)part[t][v];
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  };
+  for (int ch = 0; ch < nch; ch += 2) {
+    chunk(std::integral_constant<int, 0>{}, ch);
+    if (ch + 1 < nch) chunk(std::integral_constant<int, 1>{}, ch + 1);
   }
-  epilogue(L, row0, start, len, acc, R, rowsq, colsq, want_rowsq, want_colsq, (int)blockIdx.x);
+  epilogue<RT, NW>(L, row0, start, len, acc, R, rowsq, colsq, want_rowsq, want_colsq,
+                   (int)blockIdx.x);
 }
 
 // FP32 tiles with 8 < l <= 16: the product on v_mfma_f32_16x16x4f32, whose 16
@@ -343,19 +386,16 @@ __global__ __launch_bounds__(256) void k_fused_fp32(Layout L, const double* __re
 // lane % 16, column lane / 16) and the matrix cores accumulate
 // part[r][i] += delta^T[r][j] K^T[j][i]. FP32 sums per chunk, FP64 across chunks.
 template <int KERN, int DV, int DP, int RT>
-__global__ __launch_bounds__(kRowsWG / (16 * RT) * 64) void k_fused_fp32h(Layout L, const double* __restrict__ xv,
-                                                     const float* __restrict__ dtile,
-                                                     const Ctl* __restrict__ ctl, int block,
-                                                     float* __restrict__ R,
-                                                     float* __restrict__ rowsq,
-                                                     float* __restrict__ colsq, int want_rowsq,
-                                                     int want_colsq) {
+__global__ __launch_bounds__(kRowsWG / (16 * RT) * 64) void k_fused_fp32h(
+    Layout L, const double* __restrict__ xv, const double* __restrict__ xn,
+    const float* __restrict__ dtile, const Ctl* __restrict__ ctl, int block,
+    float* __restrict__ R, float* __restrict__ rowsq, float* __restrict__ colsq, int want_rowsq,
+    int want_colsq) {
   constexpr int NH = 16;                     // right-hand sides of the tile
   constexpr int NW = kRowsWG / (16 * RT);    // waves of the workgroup
-  constexpr int NT = 64 * NW;                // its threads
-  __shared__ double sx[kChunk][DP];
-  __shared__ double sn[kChunk];
-  __shared__ float sd[kChunk][NH];
+  __shared__ __attribute__((aligned(16))) double sx[2][kChunk][DP];
+  __shared__ __attribute__((aligned(16))) double sn[2][kChunk];
+  __shared__ __attribute__((aligned(16))) float sd[2][kChunk][NH];
   __shared__ float red[NW][NH];
   const int blk = resolve_block(block, ctl, L.m);
   if (blk < 0) return;
@@ -367,26 +407,29 @@ __global__ __launch_bounds__(kRowsWG / (16 * RT) * 64) void k_fused_fp32h(Layout
   const int ln = lane % 16, lg = lane / 16;
   const int64_t row0 = (int64_t)blockIdx.x * kRowsWG + wave * 16 * RT;
 
-  double xr[RT][DV], nr[RT];
+  stage_async<DP, NH, NW>(xv, xn, dtile, start, 0, &sx[0][0][0], sn[0], &sd[0][0][0]);
+  double xr[RT][DV], nr[RT];  // -2 v_i and |v_i|^2
 #pragma unroll
   for (int t = 0; t < RT; ++t) {
 #pragma unroll
-    for (int k = 0; k < DV; ++k) xr[t][k] = xv[(row0 + 16 * t + ln) * DP + k];
-    nr[t] = norm2<DV>(xr[t]);
+    for (int k = 0; k < DV; ++k) xr[t][k] = -2.0 * xv[(row0 + 16 * t + ln) * DP + k];
+    nr[t] = xn[row0 + 16 * t + ln];
   }
   double acc[RT][4];
 #pragma unroll
   for (int t = 0; t < RT; ++t)
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[t][q] = 0.0;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
 
-  for (int ch = 0; ch < nch; ++ch) {
-    const int64_t cb = start + (int64_t)ch * kChunk;
-    __syncthreads();
-    stage_cols<DV, DP>(xv, cb, &sx[0][0], sn);
-    for (int e = threadIdx.x; e < kChunk * NH; e += NT)
-      sd[e / NH][e % NH] = dtile[((int64_t)ch * kChunk + e / NH) * kMaxL + e % NH];
-    __syncthreads();
+  // One chunk from buffer B (a compile-time constant), the next chunk's copies
+  // going into the other, as in k_fused_fp32.
+  auto chunk = [&](auto buf, int ch) {
+    constexpr int B = decltype(buf)::value;
+    if (ch + 1 < nch)
+      stage_async<DP, NH, NW>(xv, xn, dtile, start, ch + 1, &sx[B ^ 1][0][0], sn[B ^ 1],
+                              &sd[B ^ 1][0][0]);
     f32x4 part[RT];
 #pragma unroll
     for (int t = 0; t < RT; ++t) part[t] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -395,9 +438,9 @@ __global__ __launch_bounds__(kRowsWG / (16 * RT) * 64) void k_fused_fp32h(Layout
       const int jj = 4 * st + lg;  // this lane's chunk column
       double xc[DV];
 #pragma unroll
-      for (int k = 0; k < DV; ++k) xc[k] = sx[jj][k];
-      const double nc = sn[jj];
-      const float dv = sd[jj][ln];
+      for (int k = 0; k < DV; ++k) xc[k] = sx[B][jj][k];
+      const double nc = sn[B][jj];
+      const float dv = sd[B][jj][ln];
 #pragma unroll
       for (int t = 0; t < RT; ++t) {
         const float kv = kmap_acc<KERN>(dist2n<DV>(xr[t], nr[t], xc, nc));
@@ -408,6 +451,12 @@ __global__ __launch_bounds__(kRowsWG / (16 * RT) * 64) void k_fused_fp32h(Layout
     for (int t = 0; t < RT; ++t)
 #pragma unroll
       for (int q = 0; q < 4; ++q) acc[t][q] += (double)part[t][q];
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  };
+  for (int ch = 0; ch < nch; ch += 2) {
+    chunk(std::integral_constant<int, 0>{}, ch);
+    if (ch + 1 < nch) chunk(std::integral_constant<int, 1>{}, ch + 1);
   }
 
   // lane holds acc[t][q]: row row0 + 16 t + lane % 16, right-hand side c = 4 (lane / 16) + q
@@ -627,7 +676,7 @@ __device__ __forceinline__ void split_body(const Layout& L, const double* __rest
 #pragma unroll
       for (int v = 0; v < 16; ++v) acc[t][v] += (double)part[t][v];
   }
-  epilogue(L, row0, start, len, acc, R, rowsq, colsq, want_rowsq, want_colsq, wg);
+  epilogue<2, 4>(L, row0, start, len, acc, R, rowsq, colsq, want_rowsq, want_colsq, wg);
 }
 
 template <int KERN, int DV, int DP>
@@ -735,6 +784,10 @@ hipError_t launch_fp32v(const Layout& L, const Dev& D, int32_t block, float* R, 
 // lane within the register budget of four waves per SIMD; four tiles held two.
 constexpr int kTilesH = 2;
 constexpr int kThreadsH = kRowsWG / (16 * kTilesH) * 64;
+// Row tiles per wave of the 32-row kernel. One tile (eight waves) raises the
+// occupancy but doubles the LDS reads per kernel value, and is slower.
+constexpr int kTiles32 = 2;
+constexpr int kThreads32 = kRowsWG / (32 * kTiles32) * 64;
 
 template <int KERN>
 hipError_t launch_fp32(const Layout& L, const Dev& D, int32_t block, float* R, bool wr, bool wc,
@@ -743,16 +796,16 @@ hipError_t launch_fp32(const Layout& L, const Dev& D, int32_t block, float* R, b
   if (L.l <= 2) return launch_fp32v<KERN, 2>(L, D, block, R, wr, wc, st);
   if (L.l <= 4) return launch_fp32v<KERN, 4>(L, D, block, R, wr, wc, st);
   if (L.l <= 8) return launch_fp32v<KERN, 8>(L, D, block, R, wr, wc, st);
-  const dim3 g(L.nwg), t(256);
+  const dim3 g(L.nwg);
   const float* dt = (const float*)D.dtile;
   const bool half = L.l <= 16;
 #define AP_FP32(DV, DP)                                                                          \
   if (half)                                                                                      \
     hipLaunchKernelGGL((k_fused_fp32h<KERN, DV, DP, kTilesH>), g, dim3(kThreadsH), 0, st, L,     \
-                       D.xv, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc);           \
+                       D.xv, D.xn, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc);     \
   else                                                                                           \
-    hipLaunchKernelGGL((k_fused_fp32<KERN, DV, DP>), g, t, 0, st, L, D.xv, dt, D.ctl, block, R,  \
-                       D.rowsq, D.colsq, (int)wr, (int)wc)
+    hipLaunchKernelGGL((k_fused_fp32<KERN, DV, DP, kTiles32>), g, dim3(kThreads32), 0, st, L,    \
+                       D.xv, D.xn, dt, D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc)
   if (L.d == 3) {
     AP_FP32(3, 4);
   } else {
