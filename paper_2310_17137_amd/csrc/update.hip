@@ -276,13 +276,20 @@ __device__ __forceinline__ void stage_async(const double* __restrict__ xv,
                                             const double* __restrict__ xn,
                                             const float* __restrict__ dtile, int64_t start,
                                             int ch, double* sx, double* sn, float* sd) {
-  constexpr int QR = NS / 4;  // lanes per step row
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int64_t cb = start + (int64_t)ch * kChunk;
   const float* d0 = dtile + (int64_t)ch * kChunk * kMaxL;
-  for (int q = wave; q < kChunk * NS / 256; q += NW) {
-    const int row = (64 / QR) * q + lane / QR;
-    __builtin_amdgcn_global_load_lds(d0 + row * kMaxL + 4 * (lane % QR), sd + 256 * q, 16, 0, 0);
+  if constexpr (NS >= 4) {  // step rows in 16-byte pieces, QR per row
+    constexpr int QR = NS / 4, NP = kChunk * QR;
+    for (int q = wave; 64 * q < NP; q += NW) {
+      const int pc = 64 * q + lane;
+      if (pc < NP)
+        __builtin_amdgcn_global_load_lds(d0 + (pc / QR) * kMaxL + 4 * (pc % QR), sd + 256 * q, 16,
+                                         0, 0);
+    }
+  } else {  // one or two values per row: 4-byte pieces, one wave-load
+    if (wave == 0 && lane < kChunk * NS)
+      __builtin_amdgcn_global_load_lds(d0 + (lane / NS) * kMaxL + lane % NS, sd, 4, 0, 0);
   }
   for (int q = wave; q < kChunk * DP / 128; q += NW)
     __builtin_amdgcn_global_load_lds(xv + cb * DP + 128 * q + 2 * lane, sx + 128 * q, 16, 0, 0);
@@ -514,16 +521,15 @@ __global__ __launch_bounds__(kRowsWG / (16 * RT) * 64) void k_fused_fp32h(
 // chunk's l sums accumulate in FP32 and the chunk sums in FP64, as in the
 // matrix-core kernel.
 template <int KERN, int DV, int DP, int NV>
-__global__ __launch_bounds__(256) void k_fused_fp32v(Layout L, const double* __restrict__ xv,
-                                                     const float* __restrict__ dtile,
-                                                     const Ctl* __restrict__ ctl, int block,
-                                                     float* __restrict__ R,
-                                                     float* __restrict__ rowsq,
-                                                     float* __restrict__ colsq, int want_rowsq,
-                                                     int want_colsq) {
-  __shared__ double sx[kChunk][DP];
-  __shared__ double sn[kChunk];
-  __shared__ float sd[kChunk][NV];
+__global__ __launch_bounds__(256) void k_fused_fp32v(
+    Layout L, const double* __restrict__ xv, const double* __restrict__ xn,
+    const float* __restrict__ dtile, const Ctl* __restrict__ ctl, int block,
+    float* __restrict__ R, float* __restrict__ rowsq, float* __restrict__ colsq, int want_rowsq,
+    int want_colsq) {
+  constexpr int NW = 4;
+  __shared__ __attribute__((aligned(16))) double sx[2][kChunk][DP];
+  __shared__ __attribute__((aligned(16))) double sn[2][kChunk];
+  __shared__ __attribute__((aligned(16))) float sd[2][kChunk][NV];
   __shared__ float red[4][NV];
   const int blk = resolve_block(block, ctl, L.m);
   if (blk < 0) return;
@@ -534,32 +540,40 @@ __global__ __launch_bounds__(256) void k_fused_fp32v(Layout L, const double* __r
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int64_t row = (int64_t)blockIdx.x * kRowsWG + threadIdx.x;
 
-  double xr[DV];
+  stage_async<DP, NV, NW>(xv, xn, dtile, start, 0, &sx[0][0][0], sn[0], &sd[0][0][0]);
+  double xr[DV];  // -2 v_i
 #pragma unroll
-  for (int k = 0; k < DV; ++k) xr[k] = xv[row * DP + k];
-  const double nr = norm2<DV>(xr);
+  for (int k = 0; k < DV; ++k) xr[k] = -2.0 * xv[row * DP + k];
+  const double nr = xn[row];
   double acc[NV];
 #pragma unroll
   for (int c = 0; c < NV; ++c) acc[c] = 0.0;
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
 
-  for (int ch = 0; ch < nch; ++ch) {
-    const int64_t cb = start + (int64_t)ch * kChunk;
-    __syncthreads();
-    stage_cols<DV, DP>(xv, cb, &sx[0][0], sn);
-    for (int e = threadIdx.x; e < kChunk * NV; e += 256)
-      sd[e / NV][e % NV] = dtile[((int64_t)ch * kChunk + e / NV) * kMaxL + e % NV];
-    __syncthreads();
+  // double-buffered chunks, as in k_fused_fp32
+  auto chunk = [&](auto buf, int ch) {
+    constexpr int B = decltype(buf)::value;
+    if (ch + 1 < nch)
+      stage_async<DP, NV, NW>(xv, xn, dtile, start, ch + 1, &sx[B ^ 1][0][0], sn[B ^ 1],
+                              &sd[B ^ 1][0][0]);
     float part[NV];
 #pragma unroll
     for (int c = 0; c < NV; ++c) part[c] = 0.f;
 #pragma unroll 4
     for (int j = 0; j < kChunk; ++j) {
-      const float kv = kmap_acc<KERN>(dist2n<DV>(xr, nr, sx[j], sn[j]));
+      const float kv = kmap_acc<KERN>(dist2n<DV>(xr, nr, sx[B][j], sn[B][j]));
 #pragma unroll
-      for (int c = 0; c < NV; ++c) part[c] = fmaf(kv, sd[j][c], part[c]);
+      for (int c = 0; c < NV; ++c) part[c] = fmaf(kv, sd[B][j][c], part[c]);
     }
 #pragma unroll
     for (int c = 0; c < NV; ++c) acc[c] += (double)part[c];
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+  };
+  for (int ch = 0; ch < nch; ch += 2) {
+    chunk(std::integral_constant<int, 0>{}, ch);
+    if (ch + 1 < nch) chunk(std::integral_constant<int, 1>{}, ch + 1);
   }
 
   const bool live = row < L.n;
@@ -761,8 +775,8 @@ hipError_t launch_fp32v(const Layout& L, const Dev& D, int32_t block, float* R, 
   const dim3 g(L.nwg), t(256);
   const float* dt = (const float*)D.dtile;
 #define AP_FP32V(DV, DP)                                                                  \
-  hipLaunchKernelGGL((k_fused_fp32v<KERN, DV, DP, NV>), g, t, 0, st, L, D.xv, dt, D.ctl, \
-                     block, R, D.rowsq, D.colsq, (int)wr, (int)wc)
+  hipLaunchKernelGGL((k_fused_fp32v<KERN, DV, DP, NV>), g, t, 0, st, L, D.xv, D.xn, dt, \
+                     D.ctl, block, R, D.rowsq, D.colsq, (int)wr, (int)wc)
   if (L.d == 3) {
     AP_FP32V(3, 4);
   } else {
