@@ -95,7 +95,8 @@ struct Layout {
   int32_t dp;            // prepared-feature stride (d rounded up to 4)
   int32_t nwg;           // workgroups of the fused update: n_pad / kRowsWG
   int32_t nwg_res;       // workgroups of the true residual
-  size_t off_ctl, off_xs, off_xn, off_xrow, off_xcol, off_kinv, off_dinv, off_panel, off_delta,
+  size_t off_ctl, off_xs, off_xn, off_xu, off_xun, off_xrow, off_xcol, off_kinv, off_dinv,
+      off_panel, off_delta,
       off_bspart, off_dtile, off_rowsq, off_colsq, off_blocknorm, off_respart, off_mupart,
       off_desc, off_gpart;
   int32_t nwg_mll;       // workgroups of the MLL gradient: 64 rows each
@@ -106,6 +107,8 @@ struct Dev {  // device pointers into one problem's workspace
   Ctl* ctl;
   double* xv;            // FP32 and split paths: n_pad x dp prepared features
   double* xn;            // FP32 and split paths: n_pad norms |v|^2 of the prepared features
+  double* xu;            // FP64 tiles: n_pad x dp centred features u = (x - mu) / ell
+  double* xun;           // FP64 tiles: n_pad norms |u|^2
   uint16_t* xrow;        // BF16 path: n_pad x 16 ks (row-role operand)
   uint16_t* xcol;        // BF16 path: n_pad x 16 ks (column-role operand)
   double* kinv;          // m x b_pad x b_pad

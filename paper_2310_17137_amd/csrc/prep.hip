@@ -41,6 +41,9 @@ bool make_layout(int64_t n, int32_t d, int32_t l, int32_t b, int32_t kernel, int
   o.off_ctl = take(sizeof(Ctl));
   o.off_xs = take(tile == 0 || tile == 2 ? (size_t)o.n_pad * o.dp * sizeof(double) : 0);
   o.off_xn = take(tile == 0 || tile == 2 ? (size_t)o.n_pad * sizeof(double) : 0);
+  // every mode: a handle may move to FP64 tiles (ap_set_tile, the solve's escalation)
+  o.off_xu = take((size_t)o.n_pad * o.dp * sizeof(double));
+  o.off_xun = take((size_t)o.n_pad * sizeof(double));
   o.off_xrow = take(tile == 1 ? (size_t)o.n_pad * 16 * o.ks * 2 : 0);
   o.off_xcol = take(tile == 1 ? (size_t)o.n_pad * 16 * o.ks * 2 : 0);
   o.off_kinv = take((size_t)o.m * o.b_pad * o.b_pad * sizeof(double));
@@ -68,6 +71,8 @@ Dev bind(const Layout& L, void* ws) {
   D.ctl = (Ctl*)(base + L.off_ctl);
   D.xv = (double*)(base + L.off_xs);
   D.xn = (double*)(base + L.off_xn);
+  D.xu = (double*)(base + L.off_xu);
+  D.xun = (double*)(base + L.off_xun);
   D.xrow = (uint16_t*)(base + L.off_xrow);
   D.xcol = (uint16_t*)(base + L.off_xcol);
   D.kinv = (double*)(base + L.off_kinv);
@@ -144,8 +149,10 @@ __global__ void k_mu_final(Layout L, const double* __restrict__ part, Ctl* ctl) 
   }
 }
 
-// Prepared copies of the features, v = (x - mu) / ell * c (one thread per row).
-// FP32 and split paths: xv[i] = v in FP64, differenced and squared in FP64 by
+// Prepared copies of the features (one thread per row). Every mode: the FP64
+// tiles' u = (x - mu) / ell and |u|^2 (summed in feature order with FMAs), the
+// values the FP64-tile update stages. Then v = u * c by mode. FP32 and split
+// paths: xv[i] = v in FP64, differenced and squared in FP64 by
 // the fused update, and xn[i] = |v|^2 summed in feature order with FMAs (the
 // order of the fused update's own norms). BF16 path: v = vh + vl (two BF16 terms), |v|^2 = nh + nm + nl
 // (three BF16 terms), and the row / column operands
@@ -155,12 +162,24 @@ __global__ void k_mu_final(Layout L, const double* __restrict__ part, Ctl* ctl) 
 // vl_i.vl_j term dropped). Padding rows (i >= n) are zero.
 __global__ __launch_bounds__(256) void k_prep(Layout L, Params P, const float* __restrict__ X,
                                               const Ctl* __restrict__ ctl, double* __restrict__ xv,
-                                              double* __restrict__ xn, uint16_t* __restrict__ xrow,
+                                              double* __restrict__ xn, double* __restrict__ xu,
+                                              double* __restrict__ xun,
+                                              uint16_t* __restrict__ xrow,
                                               uint16_t* __restrict__ xcol) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= L.n_pad) return;
   const double c = feat_scale(L.kernel);
   const int d = L.d;
+  {
+    double a = 0.0;
+    for (int k = 0; k < L.dp; ++k) {
+      double u = 0.0;
+      if (i < L.n && k < d) u = ((double)X[i * d + k] - ctl->mu[k]) / P.ell[k];
+      xu[i * L.dp + k] = u;
+      a = fma(u, u, a);
+    }
+    xun[i] = a;
+  }
   if (L.tile == 0 || L.tile == 2) {
     double a = 0.0;
     for (int k = 0; k < L.dp; ++k) {
@@ -172,7 +191,7 @@ __global__ __launch_bounds__(256) void k_prep(Layout L, Params P, const float* _
     xn[i] = a;
     return;
   }
-  if (L.tile != 1) return;  // the FP64-tile path reads X itself
+  if (L.tile != 1) return;  // the FP64-tile path stages xu
   const int kf = 16 * L.ks;
   uint16_t* r = xrow + i * kf;
   uint16_t* q = xcol + i * kf;
@@ -495,8 +514,8 @@ hipError_t launch_prep(const Layout& L, const Dev& D, const Params& P, const flo
   hipLaunchKernelGGL(k_mu_partial, dim3(256), dim3(256), 0, st, L, X, D.mupart);
   hipLaunchKernelGGL(k_mu_final, dim3(1), dim3(64), 0, st, L, D.mupart, D.ctl);
   unsigned g = (unsigned)((L.n_pad + 255) / 256);
-  hipLaunchKernelGGL(k_prep, dim3(g), dim3(256), 0, st, L, P, X, D.ctl, D.xv, D.xn, D.xrow,
-                     D.xcol);
+  hipLaunchKernelGGL(k_prep, dim3(g), dim3(256), 0, st, L, P, X, D.ctl, D.xv, D.xn, D.xu, D.xun,
+                     D.xrow, D.xcol);
   return hipGetLastError();
 }
 
