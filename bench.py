@@ -56,24 +56,24 @@ TILE_NAMES = {0: "fp32", 1: "bf16", 2: "split", 3: "fp64"}
 # only for the kernel sources it was taken on (sha256 over these files).
 MEASURED_TRAFFIC = {
     ("fp64", "c3"): {
-        "bytes": 138827.0 * 1024 * 2.0 + 250001.0 * 1024 * 1.0,
+        "bytes": 166359.0 * 1024 * 2.0 + 250001.0 * 1024 * 1.0,
         "files": ("update64.hip", "kmap64.h", "ap_internal.h"),
-        "sha256": "47fe79259ca7e8cc5f9fe3103236d1312c114a5a3f151562d6e887b48d5fe4ea",
+        "sha256": "caa1809aafd0e1667ef784c99fbd84d42483415e704dacdcef100f2ba65669fa",
     },
     ("fp32", "c3"): {
-        "bytes": 165342.0 * 1024 * 2.0 + 250001.0 * 1024 * 1.0,
+        "bytes": 165349.0 * 1024 * 2.0 + 250001.0 * 1024 * 1.0,
         "files": ("update.hip", "ap_internal.h"),
-        "sha256": "c2742a03aabc4419c0ee0dd370453a795cb46549cc2a4292877c57148c192292",
+        "sha256": "aa70e0cf5a7214128b91b538590b8cfef56e639c4c2c68f4e1d419ff5e1f20fd",
     },
     ("fp32", "c2"): {
-        "bytes": 18215.0 * 1024 * 2.0 + 16385.0 * 1024 * 1.0,
+        "bytes": 18221.0 * 1024 * 2.0 + 16385.0 * 1024 * 1.0,
         "files": ("update.hip", "ap_internal.h"),
-        "sha256": "c2742a03aabc4419c0ee0dd370453a795cb46549cc2a4292877c57148c192292",
+        "sha256": "aa70e0cf5a7214128b91b538590b8cfef56e639c4c2c68f4e1d419ff5e1f20fd",
     },
     ("split", "c3"): {
-        "bytes": 157975.0 * 1024 * 2.0 + 250001.0 * 1024 * 1.0,
+        "bytes": 157972.0 * 1024 * 2.0 + 250001.0 * 1024 * 1.0,
         "files": ("update.hip", "ap_internal.h"),
-        "sha256": "c2742a03aabc4419c0ee0dd370453a795cb46549cc2a4292877c57148c192292",
+        "sha256": "aa70e0cf5a7214128b91b538590b8cfef56e639c4c2c68f4e1d419ff5e1f20fd",
     },
 }
 
@@ -824,12 +824,12 @@ def main():
     kname, mfma_per_entry = fused_kernel(main_tile, w.d, w.l)
     mfma_flops_launch = mfma_per_entry * entries_per_launch
     # R read and written (FP32) plus the row features: the FP64 prepared
-    # copies (stride d rounded up to 4) on FP32 and split tiles, with their
-    # FP64 norms on FP32 tiles, X itself on FP64 tiles
-    if main_tile == ap.TILE_FP64:
-        feat = w.n * w.d * 4
+    # copies (stride d rounded up to 4), with their FP64 norms on FP32 and
+    # FP64 tiles; the BF16 row operand (16 KS values) on BF16 tiles
+    if main_tile == ap.TILE_BF16:
+        feat = w.n * 2 * 16 * ((3 * w.d + 6 + 15) // 16)
     else:
-        feat = w.n * (((w.d + 3) // 4 * 4) * 8 + (8 if main_tile == ap.TILE_FP32 else 0))
+        feat = w.n * (((w.d + 3) // 4 * 4) * 8 + (0 if main_tile == ap.TILE_SPLIT else 8))
     bytes_launch = 2.0 * w.n * w.l * 4 + feat
     roofline = {"bound": "mfma" if mfma_per_entry else "alu", "achieved": achieved, "peak": peak,
                 "unit": "TFLOP/s", "frac": achieved / peak,
