@@ -58,22 +58,22 @@ MEASURED_TRAFFIC = {
     ("fp64", "c3"): {
         "bytes": 166359.0 * 1024 * 2.0 + 250001.0 * 1024 * 1.0,
         "files": ("update64.hip", "kmap64.h", "ap_internal.h"),
-        "sha256": "caa1809aafd0e1667ef784c99fbd84d42483415e704dacdcef100f2ba65669fa",
+        "sha256": "017f90125a3ba80d8cb33d609b978252156189cee168fdf37db662152a8fcbd8",
     },
     ("fp32", "c3"): {
         "bytes": 165349.0 * 1024 * 2.0 + 250001.0 * 1024 * 1.0,
         "files": ("update.hip", "ap_internal.h"),
-        "sha256": "aa70e0cf5a7214128b91b538590b8cfef56e639c4c2c68f4e1d419ff5e1f20fd",
+        "sha256": "39d9d8dcb024ffd26c0b5cf0294aa0247a0b4e115e6867da21b2e964d9a6861a",
     },
     ("fp32", "c2"): {
         "bytes": 18221.0 * 1024 * 2.0 + 16385.0 * 1024 * 1.0,
         "files": ("update.hip", "ap_internal.h"),
-        "sha256": "aa70e0cf5a7214128b91b538590b8cfef56e639c4c2c68f4e1d419ff5e1f20fd",
+        "sha256": "39d9d8dcb024ffd26c0b5cf0294aa0247a0b4e115e6867da21b2e964d9a6861a",
     },
     ("split", "c3"): {
         "bytes": 157972.0 * 1024 * 2.0 + 250001.0 * 1024 * 1.0,
         "files": ("update.hip", "ap_internal.h"),
-        "sha256": "aa70e0cf5a7214128b91b538590b8cfef56e639c4c2c68f4e1d419ff5e1f20fd",
+        "sha256": "39d9d8dcb024ffd26c0b5cf0294aa0247a0b4e115e6867da21b2e964d9a6861a",
     },
 }
 

@@ -80,16 +80,16 @@ __device__ __forceinline__ float kmap_acc(double a) {
 }
 
 // FP64 squared distance of a row's prepared features v_i (norm ni) to a staged
-// column's, through the norm expansion |v_i|^2 + |v_j|^2 - 2 v_i.v_j with the
-// column held as -2 v_j and its norm nj: d + 1 FP64 operations instead of 2d.
-// The features are centred and scaled, so |v|^2 stays within a few hundred
-// and the cancellation leaves an absolute error near 1e-13, far below the
-// FP32 map's rounding; the Matern maps clamp the result at 0.
+// column's v_j (norm nj), through the norm expansion |v_i|^2 + |v_j|^2 -
+// 2 v_i.v_j with the row held as m2 = -2 v_i: d + 1 FP64 operations instead
+// of 2d. The features are centred and scaled, so |v|^2 stays within a few
+// hundred and the cancellation leaves an absolute error near 1e-13, far below
+// the FP32 map's rounding; the Matern maps clamp the result at 0.
 template <int DV>
-__device__ __forceinline__ double dist2n(const double* xr, double ni, const double* m2, double nj) {
+__device__ __forceinline__ double dist2n(const double* m2, double ni, const double* xc, double nj) {
   double a = ni + nj;
 #pragma unroll
-  for (int k = 0; k < DV; ++k) a = fma(xr[k], m2[k], a);
+  for (int k = 0; k < DV; ++k) a = fma(m2[k], xc[k], a);
   return a;
 }
 
@@ -104,28 +104,6 @@ __device__ __forceinline__ double dist2(const double* xr, const double* xc) {
     a = fma(df, df, a);
   }
   return a;
-}
-
-template <int DV>
-__device__ __forceinline__ double norm2(const double* x) {
-  double a = 0.0;
-#pragma unroll
-  for (int k = 0; k < DV; ++k) a = fma(x[k], x[k], a);
-  return a;
-}
-
-// Stage a chunk's columns (rows cb .. cb + 31 of the prepared features) as
-// -2 v_j and their norms |v_j|^2. The caller brackets it with barriers.
-template <int DV, int DP>
-__device__ __forceinline__ void stage_cols(const double* __restrict__ xv, int64_t cb, double* sx,
-                                           double* sn) {
-  for (int e = threadIdx.x; e < kChunk * DP; e += blockDim.x) sx[e] = -2.0 * xv[cb * DP + e];
-  if (threadIdx.x < kChunk) {
-    double v[DV];
-#pragma unroll
-    for (int k = 0; k < DV; ++k) v[k] = xv[(cb + threadIdx.x) * DP + k];
-    sn[threadIdx.x] = norm2<DV>(v);
-  }
 }
 
 __device__ __forceinline__ bf16x8 load_bf16x8(const uint16_t* p) {

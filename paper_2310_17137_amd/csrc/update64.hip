@@ -82,10 +82,10 @@ __device__ __forceinline__ void stage_async64(const double* __restrict__ xu,
 }
 
 template <int DV>
-__device__ __forceinline__ double dist2n64(const double* u, double nu, const double* m2, double nj) {
-  double a = nu + nj;
+__device__ __forceinline__ double dist2n64(const double* m2, double nu, const double* uc, double nj) {
+  double a = nu + nj;  // row held as m2 = -2 u_i, column as u_j
 #pragma unroll
-  for (int k = 0; k < DV; ++k) a = fma(u[k], m2[k], a);
+  for (int k = 0; k < DV; ++k) a = fma(m2[k], uc[k], a);
   return a;
 }
 
