@@ -326,6 +326,9 @@ def test_single_point_system_is_solved_in_one_update(tile):
     (2, 1, 3, 1),      # two unit blocks
     (300, 1, 9, 100),  # one feature; l = 9 takes the FP32 16-row matrix tile
     (65, 20, 32, 64),  # the widest features with l = 32, a last block of one point
+    # a last block of 24 points: its 64-column FP64-tile step reaches 40 rows
+    # past n, beyond the 32 padding rows (the staged sources are clamped)
+    (224, 3, 32, 100),
 ])
 def test_degenerate_shapes_match_oracle(n, d, l, b, tile):
     w = gen.small(22, n, d, l, b, kernel=apo.RBF, noise=0.1, ell=0.6 if d == 1 else 3.0)
