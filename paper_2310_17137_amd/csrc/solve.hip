@@ -53,11 +53,28 @@ __device__ __forceinline__ void bs_partial_body(const Layout& L, const double* _
   double acc[LB];
 #pragma unroll
   for (int c = 0; c < LB; ++c) acc[c] = 0.0;
-  for (int qq = wave; qq < slice; qq += 4) {
-    const double kv = K[(size_t)(q0 + qq) * L.b_pad + i];
-    const double* rq = smem + qq * LB;
+  // The wave's rows q of the inverse in batches of kBsAhead: the batch's loads
+  // are issued together (one at a time, each would wait out the memory latency)
+  // and the sum keeps its q order. The empty asm keeps each q's LDS reads after
+  // the previous q's, so the batch does not hold every staged row in registers.
+  constexpr int kBsAhead = 8;
+  for (int qb = wave; qb < slice; qb += 4 * kBsAhead) {
+    double kv[kBsAhead];
 #pragma unroll
-    for (int c = 0; c < LB; ++c) acc[c] = fma(kv, rq[c], acc[c]);
+    for (int j = 0; j < kBsAhead; ++j) {
+      const int qq = qb + 4 * j;
+      kv[j] = qq < slice ? K[(size_t)(q0 + qq) * L.b_pad + i] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < kBsAhead; ++j) {
+      const int qq = qb + 4 * j;
+      if (qq < slice) {
+        asm volatile("" ::: "memory");
+        const double* rq = smem + qq * LB;
+#pragma unroll
+        for (int c = 0; c < LB; ++c) acc[c] = fma(kv[j], rq[c], acc[c]);
+      }
+    }
   }
   __syncthreads();
 #pragma unroll
