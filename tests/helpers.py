@@ -103,7 +103,7 @@ def tile_trajectory(p, epochs: int, mode: str = "fp32", log=None):
     """Cyclic epochs of the FP64 oracle beside a perfect reduced-precision
     tile implementation of the same updates. Returns, per epoch, the oracle's
     W and the relative distance (Frobenius) of the emulated run's W from it:
-    the rounding floor the GPU's tiles are judged against.
+    the rounding floor the GPU's tiles are measured against.
 
     mode "fp32": every kernel value K^_ij rounded once to FP32 and the step
     s delta rounded to FP32; each 32-column chunk summed on an FP32
