@@ -63,17 +63,17 @@ MEASURED_TRAFFIC = {
     ("fp32", "c3"): {
         "bytes": 165349.0 * 1024 * 2.0 + 250001.0 * 1024 * 1.0,
         "files": ("update.hip", "ap_internal.h"),
-        "sha256": "39d9d8dcb024ffd26c0b5cf0294aa0247a0b4e115e6867da21b2e964d9a6861a",
+        "sha256": "3bf87ff9ab342369ef748b81ffb2290f935d5188b2562c9cfee57cd1e941693d",
     },
     ("fp32", "c2"): {
         "bytes": 18221.0 * 1024 * 2.0 + 16385.0 * 1024 * 1.0,
         "files": ("update.hip", "ap_internal.h"),
-        "sha256": "39d9d8dcb024ffd26c0b5cf0294aa0247a0b4e115e6867da21b2e964d9a6861a",
+        "sha256": "3bf87ff9ab342369ef748b81ffb2290f935d5188b2562c9cfee57cd1e941693d",
     },
     ("split", "c3"): {
         "bytes": 157972.0 * 1024 * 2.0 + 250001.0 * 1024 * 1.0,
         "files": ("update.hip", "ap_internal.h"),
-        "sha256": "39d9d8dcb024ffd26c0b5cf0294aa0247a0b4e115e6867da21b2e964d9a6861a",
+        "sha256": "3bf87ff9ab342369ef748b81ffb2290f935d5188b2562c9cfee57cd1e941693d",
     },
 }
 

@@ -7,13 +7,20 @@
 // Gauss-Southwell rule, eq. approximate_gauss_southwell) and per-workgroup
 // column sums of squares (the epoch-end stopping test).
 //
-// One workgroup = 4 wave64s = 256 rows; a wave owns two 32-row tiles. The block
-// is walked in chunks of 32 columns. Every chunk is a pair of 32 x 32 MFMA
-// products per row tile: S^T = X_chunk X_rows^T (tile x.x' -> kernel map in
-// registers) and acc += delta_chunk^T K_tile^T. Computing the transposed tile
-// makes the first product's accumulator layout (lane = data row, 16 chunk
-// columns) the second product's B operand, so the kernel values go from the
-// map straight into the next MFMA without leaving registers.
+// Every kernel here gives a workgroup 256 data rows and walks the block in
+// chunks of 32 columns, adding each chunk's FP32 sums into FP64 accumulators.
+// The tile modes differ in how a chunk's kernel values are formed and applied:
+//  - FP32 tiles (k_fused_fp32, k_fused_fp32h, k_fused_fp32v): FP64 squared
+//    distances on the vector units, the map in FP32, and the product with the
+//    step on the FP32 matrix cores (32 or 16 right-hand sides) or, for l <= 8,
+//    as vector FMAs;
+//  - split tiles (k_fused_split): the same FP32 kernel values, with the tile
+//    and the step each split into three BF16 terms for six BF16 products;
+//  - BF16 tiles (k_fused_bf16): two 32 x 32 MFMA products per row tile,
+//    S^T = X_chunk X_rows^T (x.x' on the BF16 matrix cores, then the map in
+//    registers) and acc += delta_chunk^T K_tile^T. The transposed tile makes the
+//    first product's accumulator layout (lane = data row, 16 chunk columns) the
+//    second product's B operand, so the kernel values never leave registers.
 #include <algorithm>
 #include <type_traits>
 
