@@ -54,7 +54,8 @@ __device__ __forceinline__ float kmap_neg(float a) {  // a = -|dv|^2
 }
 
 // Kernel map of the FP32 and split tiles: k/s from the FP64 squared distance a
-// of the prepared features, in FP32 to within about 2 ulp. The exponential runs
+// of the prepared features, in FP32 to within about 2 ulp for RBF and a few ulp
+// for the Matern maps (half an ulp on average). The exponential runs
 // on the FP32 unit from a_hi = fl32(a); the argument's rounding a_lo = a - a_hi
 // enters to first order, 2^-(a_hi + a_lo) = 2^-a_hi (1 - a_lo ln 2). The
 // Matern maps take t = sqrt(a) as t_hi = sqrt(a_hi) plus the correction
@@ -74,14 +75,17 @@ __device__ __forceinline__ float kmap_acc(double a) {
     const double thd = (double)th;
     const float ea = (float)fma(-thd, thd, a);  // a - t_hi^2, exact in FP64
     const float e = __builtin_amdgcn_exp2f(-th);
-    constexpr float kHalfLn2Sq = (float)(0.5 / (kLog2e * kLog2e));
+    // k/s = 2^-t_hi (p(t_hi) + (a - t_hi^2) c(t_hi)), the correction's factor
+    // c(t) = k'(t) / (2 t 2^-t) carrying its constants
+    constexpr double kHalfLn2Sq = 0.5 / (kLog2e * kLog2e);
     if constexpr (KERN == 1) {
-      const float k0 = fmaf(th, kInvLog2e, 1.0f) * e;
-      return fmaf(ea * -kHalfLn2Sq, e, k0);
+      const float p = fmaf(th, kInvLog2e, 1.0f);
+      return fmaf(ea, (float)-kHalfLn2Sq, p) * e;
     } else {
-      const float q = fmaf(th, kInvLog2e, 1.0f);
-      const float k0 = fmaf(th, fmaf(th, kInv3Log2e2, kInvLog2e), 1.0f) * e;
-      return fmaf(ea * q * (-kHalfLn2Sq * (1.0f / 3.0f)), e, k0);
+      constexpr float kC0 = (float)(-kHalfLn2Sq / 3.0);
+      constexpr float kC1 = (float)(-kHalfLn2Sq / (3.0 * kLog2e));
+      const float p = fmaf(th, fmaf(th, kInv3Log2e2, kInvLog2e), 1.0f);
+      return fmaf(ea, fmaf(th, kC1, kC0), p) * e;
     }
   }
 }
@@ -283,7 +287,7 @@ __device__ __forceinline__ void stage_async(const double* __restrict__ xv,
 }
 
 // FP32 tiles: the prepared features in FP64, the squared distance in FP64, the
-// kernel map in FP32 (kmap_acc, within about 2 ulp), and the product with the
+// kernel map in FP32 (kmap_acc, within a few ulp), and the product with the
 // step on v_mfma_f32_32x32x2f32 (one kernel value per lane per step). Each
 // chunk's column features, norms and step rows are staged in LDS, double-
 // buffered: chunk c + 1 is copied into one buffer while chunk c is computed
