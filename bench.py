@@ -63,19 +63,19 @@ MEASURED_TRAFFIC = {
         "sha256": "017f90125a3ba80d8cb33d609b978252156189cee168fdf37db662152a8fcbd8",
     },
     ("fp32", "c3"): {
-        "bytes": 165349.0 * 1024 * 2.0 + 250001.0 * 1024 * 1.0,
+        "bytes": 165342.0 * 1024 * 2.0 + 250001.0 * 1024 * 1.0,
         "files": ("update.hip", "ap_internal.h"),
-        "sha256": "7644be271147a276a9d56d8e2963034598a1eeac64290a1fc0f0d34f968e9a6e",
+        "sha256": "b7bb8c8dba6f46009874d96bd5cf7d9e456913f7f5b201a1b2edb086e4ad8449",
     },
     ("fp32", "c2"): {
         "bytes": 18219.0 * 1024 * 2.0 + 16385.0 * 1024 * 1.0,
         "files": ("update.hip", "ap_internal.h"),
-        "sha256": "7644be271147a276a9d56d8e2963034598a1eeac64290a1fc0f0d34f968e9a6e",
+        "sha256": "b7bb8c8dba6f46009874d96bd5cf7d9e456913f7f5b201a1b2edb086e4ad8449",
     },
     ("split", "c3"): {
         "bytes": 157972.0 * 1024 * 2.0 + 250001.0 * 1024 * 1.0,
         "files": ("update.hip", "ap_internal.h"),
-        "sha256": "7644be271147a276a9d56d8e2963034598a1eeac64290a1fc0f0d34f968e9a6e",
+        "sha256": "b7bb8c8dba6f46009874d96bd5cf7d9e456913f7f5b201a1b2edb086e4ad8449",
     },
 }
 

@@ -320,9 +320,10 @@ __global__ __launch_bounds__(kRowsWG / (32 * RT) * 64) void k_fused_fp32(
     for (int k = 0; k < DV; ++k) xr[t][k] = -2.0 * xv[(row0 + 32 * t + nl) * DP + k];
     nr[t] = xn[row0 + 32 * t + nl];
   }
-  // Each chunk's 32 products accumulate in FP32 on the matrix cores; the chunk
-  // sums then accumulate in FP64, so the rounding of the long sum over the
-  // block stays at the level of one chunk.
+  // The products of a pair of chunks (64 columns) accumulate in FP32 on the
+  // matrix cores; the pair sums then accumulate in FP64, so the rounding of the
+  // long sum over the block stays at the level of 64 products. (Pairs rather
+  // than single chunks halve the FP64 additions and their conversions.)
   f64x16 acc[RT];
 #pragma unroll
   for (int t = 0; t < RT; ++t)
@@ -333,17 +334,19 @@ __global__ __launch_bounds__(kRowsWG / (32 * RT) * 64) void k_fused_fp32(
 
   // One chunk from buffer B (a compile-time constant, so that the LDS reads
   // keep immediate offsets), the next chunk's copies going into the other.
+  f32x16 part[RT];  // FP32 sums of the current chunk pair (even ch, then ch + 1)
   auto chunk = [&](auto buf, int ch) {
     constexpr int B = decltype(buf)::value;
     // the other buffer was last read before the previous barrier
     if (ch + 1 < nch)
       stage_async<DP, kMaxL, NW>(xv, xn, dtile, start, ch + 1, &sx[B ^ 1][0][0], sn[B ^ 1],
                                  &sd[B ^ 1][0][0]);
-    f32x16 part[RT];
+    if constexpr (B == 0) {  // even chunks (buffer 0) open a pair
 #pragma unroll
-    for (int t = 0; t < RT; ++t)
+      for (int t = 0; t < RT; ++t)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) part[t][v] = 0.f;
+        for (int v = 0; v < 16; ++v) part[t][v] = 0.f;
+    }
 #pragma unroll
     for (int st = 0; st < 16; ++st) {
       const int cc = 2 * st + g;  // this lane's chunk column
@@ -358,10 +361,12 @@ __global__ __launch_bounds__(kRowsWG / (32 * RT) * 64) void k_fused_fp32(
         part[t] = __builtin_amdgcn_mfma_f32_32x32x2f32(dv, kv, part[t], 0, 0, 0);
       }
     }
+    if (B == 1 || ch + 1 >= nch) {  // odd chunks, and a last even one, close it
 #pragma unroll
-    for (int t = 0; t < RT; ++t)
+      for (int t = 0; t < RT; ++t)
 #pragma unroll
-      for (int v = 0; v < 16; ++v) acc[t][v] += (double)part[t][v];
+        for (int v = 0; v < 16; ++v) acc[t][v] += (double)part[t][v];
+    }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
   };
@@ -508,7 +513,7 @@ __global__ __launch_bounds__(kRowsWG / (16 * RT) * 64) void k_fused_fp32h(
 // workgroup, the same partials as the tile kernels); the chunk's column
 // features and step are staged in LDS and read by all lanes at once. Each
 // chunk's l sums accumulate in FP32 and the chunk sums in FP64, as in the
-// matrix-core kernel.
+// 16-row matrix-core kernel.
 template <int KERN, int DV, int DP, int NV>
 __global__ __launch_bounds__(256) void k_fused_fp32v(
     Layout L, const double* __restrict__ xv, const double* __restrict__ xn,

@@ -68,22 +68,23 @@ def _floor_lib():
         L = ctypes.CDLL(lib)
         P = ctypes.c_void_p
         L.chunk_products.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
-                                     ctypes.c_int, P]
+                                     ctypes.c_int, ctypes.c_int, P]
         L.chunk_products.restype = None
         _FLOOR_LIB = L
     return _FLOOR_LIB
 
 
-def _chunk_products(Kt, dt, group: int) -> np.ndarray:
+def _chunk_products(Kt, dt, group: int, span: int = 32) -> np.ndarray:
     """Sum_q Kt[:, q] dt[q] over a block as the matrix cores form it (see
-    tests/tile_floor.c). Kt (n x len) and dt (len x l) hold the rounded
-    operands (float32)."""
+    tests/tile_floor.c): FP32 sums over runs of span columns, `group` products
+    per rounding. Kt (n x len) and dt (len x l) hold the rounded operands
+    (float32)."""
     Kt = np.ascontiguousarray(Kt, dtype=np.float32)
     dt = np.ascontiguousarray(dt, dtype=np.float32)
     n, ln = Kt.shape
     l = dt.shape[1]
     out = np.empty((n, l))
-    _floor_lib().chunk_products(Kt.ctypes.data, dt.ctypes.data, n, ln, l, group,
+    _floor_lib().chunk_products(Kt.ctypes.data, dt.ctypes.data, n, ln, l, group, span,
                                 out.ctypes.data)
     return out
 
@@ -99,6 +100,13 @@ def fp32_product_group(l: int) -> int:
     return 2
 
 
+def fp32_sum_span(l: int) -> int:
+    """Columns the FP32 tiles sum in one FP32 accumulator before adding the sum
+    into FP64: a 32-column chunk, or a pair of chunks for the
+    v_mfma_f32_32x32x2f32 kernel (l > 16)."""
+    return 64 if l > 16 else 32
+
+
 def tile_trajectory(p, epochs: int, mode: str = "fp32", log=None):
     """Cyclic epochs of the FP64 oracle beside a perfect reduced-precision
     tile implementation of the same updates. Returns, per epoch, the oracle's
@@ -106,9 +114,9 @@ def tile_trajectory(p, epochs: int, mode: str = "fp32", log=None):
     the rounding floor the GPU's tiles are measured against.
 
     mode "fp32": every kernel value K^_ij rounded once to FP32 and the step
-    s delta rounded to FP32; each 32-column chunk summed on an FP32
-    accumulator as the FP32 tile kernel for this l forms it
-    (fp32_product_group). mode "bf16":
+    s delta rounded to FP32; each chunk (32 columns, or a 64-column pair for
+    l > 16: fp32_sum_span) summed on an FP32 accumulator as the FP32 tile
+    kernel for this l forms it (fp32_product_group). mode "bf16":
     the kernel values over s and the step s delta rounded to BF16, sixteen
     products per accumulator step (v_mfma_f32_32x32x16_bf16). In both the
     chunk sums add up in FP64, R is stored in FP32 after each update with the
@@ -117,6 +125,7 @@ def tile_trajectory(p, epochs: int, mode: str = "fp32", log=None):
     from oracle import apo
     L = apo.factor(p)
     group = fp32_product_group(p.B.shape[1])
+    span = fp32_sum_span(p.B.shape[1])
     Wo, Ro = np.zeros_like(p.B), p.B.copy()
     W, R = np.zeros_like(p.B), p.B.astype(np.float32).astype(np.float64)
     so = p.outputscale
@@ -131,7 +140,7 @@ def tile_trajectory(p, epochs: int, mode: str = "fp32", log=None):
             if mode == "bf16":
                 upd = so * _chunk_products(bf16(K / so), bf16(so * d), 16) / so
             else:
-                upd = _chunk_products(K.astype(np.float32), d.astype(np.float32), group)
+                upd = _chunk_products(K.astype(np.float32), d.astype(np.float32), group, span)
             del K
             R = (R - upd).astype(np.float32).astype(np.float64)
             R[s] = 0.0

@@ -12,7 +12,8 @@ see the same FP32 values (the oracle widened to FP64). Tolerances:
     4 u32 times the factor. Over several epochs the bar is at most twice the
     FP32-tile floor (tests.helpers.fp32_tile_floor): the distance from the
     oracle of a perfect FP32-tile run of the same updates (kernel values and
-    step correctly rounded to FP32, 32-column chunks summed in FP32, emulated
+    step correctly rounded to FP32, 32-column chunks (64-column pairs for
+    l > 16) summed in FP32, emulated
     on the CPU), printed with the GPU's error for every epoch. The FP32 sums
     inside each chunk, not the kernel values, set that floor: on the 4096-point
     recipe it is 3.4e-5 after 30 epochs, against 7e-6 with the kernel values
